@@ -1,0 +1,298 @@
+"""Seeded synthetic scenes for the differentiable MLS-MPM step.
+
+This module only draws inputs: particle positions, initial velocities and
+deformation, material constants and actuation weights. It contains none of the
+simulation arithmetic, so both the GPU path and the FP64 oracle can take their
+inputs from it.
+
+Every scene is generated in float64 and then rounded to float32; the float32
+values are what both sides receive (the oracle widens them back to float64),
+so parity measures the dynamics and not input rounding.
+
+Workloads (the paper's elastic-object simulator, Section 4.1; its own
+benchmark used a 2D scene with 6.4K particles whose grid is not stated):
+  c1   2D, 64^2 grid, 1024 particles on a jittered lattice, uniform v=(1,0), 64 steps
+  c1d  c1 with an added affine velocity, so the body deforms
+  c2   2D actuated soft body, 128^2 grid, 8192 particles in a union of rectangles,
+       4 actuators driven by a_k(t) = tanh(sum_j W_kj sin(w t + 2 pi j/4) + b_k), 512 steps
+  c3   3D, 64^3 grid, 32768 particles on a 32^3 jittered lattice, 256 steps, full tape
+  c4   3D, 128^3 grid, 262144 particles on a 64^3 lattice, 1024 steps, checkpoints every 64
+  c5   256 independent 2D scenes on their own 64^2 grids, particle counts
+       log-uniform in [500, 8000], per-scene E and nu, 256 steps
+  fd8  8 particles with random C and F, for finite-difference checks
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import Optional
+
+import numpy as np
+
+F32 = np.float32
+
+
+@dataclass
+class Scene:
+    name: str
+    dim: int
+    n_grid: int
+    dx: float
+    dt: float
+    steps: int
+    offsets: np.ndarray          # int32 [n_scenes + 1]
+    E: np.ndarray                # float32 [n_scenes]
+    nu: np.ndarray               # float32 [n_scenes]
+    vol: np.ndarray              # float32 [n_scenes] initial particle volume
+    rho: np.ndarray              # float32 [n_scenes]
+    x: np.ndarray                # float32 (N, d)
+    v: np.ndarray                # float32 (N, d)
+    C: np.ndarray                # float32 (N, d, d)
+    F: np.ndarray                # float32 (N, d, d)
+    bound: int = 3
+    gravity: float = -9.8
+    ckpt_every: int = 0          # 0: full tape
+    loss_axis: int = 0
+    loss_sign: float = 1.0
+    act_id: Optional[np.ndarray] = None   # int32 (N,) actuator column, -1 for none
+    n_act: int = 0
+    act_strength: float = 0.0
+    act_W: Optional[np.ndarray] = None    # float32 (n_act, n_sin)
+    act_b: Optional[np.ndarray] = None    # float32 (n_act,)
+    act_omega: float = 0.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_particles(self) -> int:
+        return int(self.offsets[-1])
+
+    @property
+    def n_scenes(self) -> int:
+        return len(self.offsets) - 1
+
+    def with_steps(self, steps: int, ckpt_every: Optional[int] = None) -> "Scene":
+        return replace(self, steps=int(steps), ckpt_every=self.ckpt_every if ckpt_every is None else ckpt_every)
+
+    def subset(self, scenes) -> "Scene":
+        """Scenes `scenes` of a batched scene, as a new batched scene."""
+        scenes = list(scenes)
+        idx = np.concatenate([np.arange(self.offsets[k], self.offsets[k + 1]) for k in scenes])
+        counts = [int(self.offsets[k + 1] - self.offsets[k]) for k in scenes]
+        off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+        return replace(
+            self, name=f"{self.name}[{len(scenes)}]", offsets=off, E=self.E[scenes].copy(),
+            nu=self.nu[scenes].copy(), vol=self.vol[scenes].copy(), rho=self.rho[scenes].copy(),
+            x=self.x[idx].copy(), v=self.v[idx].copy(), C=self.C[idx].copy(), F=self.F[idx].copy(),
+            act_id=None if self.act_id is None else self.act_id[idx].copy())
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).astype(F32))
+
+
+def _lattice(rng, dim, per_axis, lo, spacing, jitter):
+    """per_axis^dim points at lo + (i + 1/2) * spacing, each jittered by U(-jitter, jitter)."""
+    idx = np.stack(np.meshgrid(*([np.arange(per_axis)] * dim), indexing="ij"), axis=-1).reshape(-1, dim)
+    x = lo + (idx + 0.5) * spacing
+    return x + rng.uniform(-jitter, jitter, size=x.shape)
+
+
+def _identity(N, dim):
+    return np.broadcast_to(np.eye(dim), (N, dim, dim)).copy()
+
+
+def _single(name, dim, n_grid, dt, steps, x, v, E, nu, vol, **kw):
+    N = x.shape[0]
+    return Scene(
+        name=name, dim=dim, n_grid=n_grid, dx=1.0 / n_grid, dt=float(F32(dt)), steps=steps,
+        offsets=np.array([0, N], np.int32), E=_f32([E]), nu=_f32([nu]), vol=_f32([vol]), rho=_f32([1.0]),
+        x=_f32(x), v=_f32(v), C=_f32(np.zeros((N, dim, dim))), F=_f32(_identity(N, dim)), **kw)
+
+
+def c1(seed: int = 0) -> Scene:
+    """2D, 64^2, 1024 particles on a 32x32 lattice spaced dx/2 in [0.25, 0.5]^2,
+    jitter U(+-0.1 dx), v = (1, 0), E = 10, nu = 0.2, volume (dx/2)^2, dt = 1e-3, 64 steps,
+    loss = mean final x-coordinate."""
+    rng = np.random.default_rng(seed)
+    n = 64
+    dx = 1.0 / n
+    x = _lattice(rng, 2, 32, 0.25, dx / 2, 0.1 * dx)
+    v = np.tile([1.0, 0.0], (x.shape[0], 1))
+    return _single("c1", 2, n, 1e-3, 64, x, v, 10.0, 0.2, (dx / 2) ** 2, loss_axis=0)
+
+
+def c1d(seed: int = 0) -> Scene:
+    """c1 with v = (1, 0) + diag(1, -1) (x - (0.375, 0.375)) so that C and F evolve."""
+    s = c1(seed)
+    x = s.x.astype(np.float64)
+    v = np.array([1.0, 0.0]) + (x - 0.375) * np.array([1.0, -1.0])
+    return replace(s, name="c1d", v=_f32(v))
+
+
+def _skyline_rects(rng, n_rect, w_lo, w_hi, h_lo, h_hi, x_lo, x_hi):
+    """Axis-aligned rectangles standing on y = 0, each overlapping an earlier one in x."""
+    rects = []
+    for k in range(n_rect):
+        w = rng.uniform(w_lo, w_hi)
+        h = rng.uniform(h_lo, h_hi)
+        if k == 0:
+            x0 = rng.uniform(x_lo, max(x_lo, x_hi - w))
+        else:
+            px0, px1, _ = rects[rng.integers(0, k)]
+            x0 = rng.uniform(px0 - 0.8 * w, px1 - 0.2 * w)
+            x0 = min(max(x0, x_lo), x_hi - w)
+        rects.append((x0, x0 + w, h))
+    return rects
+
+
+def _skyline_area(rects):
+    xs = sorted({r[0] for r in rects} | {r[1] for r in rects})
+    area = 0.0
+    for a, b in zip(xs[:-1], xs[1:]):
+        mid = 0.5 * (a + b)
+        h = max([r[2] for r in rects if r[0] <= mid < r[1]] or [0.0])
+        area += (b - a) * h
+    return area
+
+
+def _sample_union(rng, rects, N):
+    """N points uniform in the union; also the index of the first rectangle containing each."""
+    x0 = min(r[0] for r in rects)
+    x1 = max(r[1] for r in rects)
+    y1 = max(r[2] for r in rects)
+    pts, ids = [], []
+    need = N
+    while need > 0:
+        c = rng.uniform([x0, 0.0], [x1, y1], size=(max(4 * need, 64), 2))
+        inside = np.zeros(len(c), bool)
+        first = np.full(len(c), -1)
+        for k, (a, b, h) in enumerate(rects):
+            hit = (c[:, 0] >= a) & (c[:, 0] < b) & (c[:, 1] < h) & ~inside
+            first[hit] = k
+            inside |= hit
+        pts.append(c[inside][:need])
+        ids.append(first[inside][:need])
+        need -= len(pts[-1])
+    return np.concatenate(pts), np.concatenate(ids)
+
+
+def c2(seed: int = 1) -> Scene:
+    """2D actuated soft body: 128^2 grid, 8192 particles uniform in a union of 4-6
+    rectangles (widths, heights U[0.05, 0.2], standing on y = 0.1, x in [0.1, 0.6]);
+    actuator column = (first containing rectangle) mod 4; a_k(t) = tanh(sum_j W_kj
+    sin(omega t + 2 pi j / 4) + b_k) with W, b ~ N(0, 0.1^2), omega = 2 pi 5, sigma_a = 10;
+    E = 10, nu = 0.2, dt = 1e-3, 512 steps; loss = -(mean final x)."""
+    rng = np.random.default_rng(seed)
+    n = 128
+    N = 8192
+    rects = _skyline_rects(rng, int(rng.integers(4, 7)), 0.05, 0.2, 0.05, 0.2, 0.1, 0.6)
+    area = _skyline_area(rects)
+    pts, first = _sample_union(rng, rects, N)
+    pts[:, 1] += 0.1
+    n_act = 4
+    W = rng.normal(0.0, 0.1, size=(n_act, 4))
+    b = rng.normal(0.0, 0.1, size=(n_act,))
+    s = _single("c2", 2, n, 1e-3, 512, pts, np.zeros((N, 2)), 10.0, 0.2, area / N, loss_axis=0,
+                loss_sign=-1.0, act_id=(first % n_act).astype(np.int32), n_act=n_act, act_strength=10.0,
+                act_W=_f32(W), act_b=_f32(b), act_omega=float(F32(2 * math.pi * 5)))
+    s.meta["rects"] = rects
+    return s
+
+
+def _c3_like(name, seed, n_grid, per_axis, dt, steps, ckpt, loss_axis):
+    rng = np.random.default_rng(seed)
+    dx = 1.0 / n_grid
+    x = _lattice(rng, 3, per_axis, 0.25, dx / 2, 0.1 * dx)
+    # Affine initial velocity diag(1, -1, 0) (x - x_c), so the block deforms.
+    v = (x - 0.375) * np.array([1.0, -1.0, 0.0])
+    return _single(name, 3, n_grid, dt, steps, x, v, 20.0, 0.3, (dx / 2) ** 3, ckpt_every=ckpt,
+                   loss_axis=loss_axis)
+
+
+def c3(seed: int = 2) -> Scene:
+    """3D, 64^3 grid, 32768 particles on a 32^3 lattice spaced dx/2 in [0.25, 0.5]^3,
+    jittered, E = 20, nu = 0.3, dt = 5e-4, 256 steps, full tape; loss = mean final height."""
+    return _c3_like("c3", seed, 64, 32, 5e-4, 256, 0, 1)
+
+
+def c4(seed: int = 3) -> Scene:
+    """3D, 128^3 grid, 262144 particles on a 64^3 lattice spaced dx/2, jittered, E = 20,
+    nu = 0.3, dt = 2.5e-4, 1024 steps, checkpoints every 64; loss = mean final x."""
+    return _c3_like("c4", seed, 128, 64, 2.5e-4, 1024, 64, 0)
+
+
+def c5(seed: int = 4, n_scenes: int = 256, steps: int = 256) -> Scene:
+    """n_scenes independent 2D scenes, each on its own 64^2 grid, with particle counts
+    N = round(exp U(ln 500, ln 8000)) in rectangle-union shapes (4 particles per cell,
+    volume (dx/2)^2), centred in x and standing on y = 0.1; E ~ U[5, 30], nu ~ U[0.1, 0.4];
+    v0 = 0; dt = 1e-3; loss = sum over scenes of the mean final x."""
+    rng = np.random.default_rng(seed)
+    n = 64
+    dx = 1.0 / n
+    vol = (dx / 2) ** 2
+    xs, counts, Es, nus = [], [], [], []
+    for _ in range(n_scenes):
+        N = int(round(math.exp(rng.uniform(math.log(500), math.log(8000)))))
+        rects = _skyline_rects(rng, int(rng.integers(4, 7)), 0.25, 1.0, 0.25, 1.0, 0.0, 1.5)
+        area0 = _skyline_area(rects)
+        scale = math.sqrt(N * vol / area0)
+        width0 = max(r[1] for r in rects) - min(r[0] for r in rects)
+        height0 = max(r[2] for r in rects)
+        sx = sy = scale
+        if width0 * sx > 0.8:          # keep the area, make it narrower and taller
+            f = 0.8 / (width0 * sx)
+            sx *= f
+            sy /= f
+        if height0 * sy > 0.8:
+            sy = 0.8 / height0
+        pts, _ = _sample_union(rng, rects, N)
+        x_min = min(r[0] for r in rects)
+        x_max = max(r[1] for r in rects)
+        pts[:, 0] = (pts[:, 0] - 0.5 * (x_min + x_max)) * sx + 0.5
+        pts[:, 1] = pts[:, 1] * sy + 0.1
+        xs.append(pts)
+        counts.append(N)
+        Es.append(rng.uniform(5.0, 30.0))
+        nus.append(rng.uniform(0.1, 0.4))
+    x = np.concatenate(xs)
+    Nt = x.shape[0]
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    ns = n_scenes
+    return Scene(
+        name="c5", dim=2, n_grid=n, dx=dx, dt=float(F32(1e-3)), steps=steps, offsets=off, E=_f32(Es),
+        nu=_f32(nus), vol=_f32(np.full(ns, vol)), rho=_f32(np.ones(ns)), x=_f32(x),
+        v=_f32(np.zeros((Nt, 2))), C=_f32(np.zeros((Nt, 2, 2))), F=_f32(_identity(Nt, 2)), loss_axis=0)
+
+
+def fd8(dim: int = 2, seed: int = 5, steps: int = 16) -> Scene:
+    """8 particles (2x4 in 2D, 2x2x2 in 3D) near the centre of a 16^d grid, spaced dx/2,
+    with F = I + 0.05 N(0,1), C ~ N(0, 1), v ~ N(0, 0.2): every term of the step is active."""
+    rng = np.random.default_rng(seed)
+    n = 16
+    dx = 1.0 / n
+    shape = (2, 4) if dim == 2 else (2, 2, 2)
+    idx = np.stack(np.meshgrid(*[np.arange(k) for k in shape], indexing="ij"), -1).reshape(-1, dim)
+    x = 0.5 + (idx - np.array(shape) / 2 + 0.5) * dx / 2 + rng.uniform(-0.1 * dx, 0.1 * dx, (8, dim))
+    s = _single(f"fd8_{dim}d", dim, n, 1e-3, steps, x, rng.normal(0, 0.2, (8, dim)), 10.0, 0.25,
+                (dx / 2) ** dim)
+    s.C = _f32(rng.normal(0.0, 1.0, (8, dim, dim)))
+    s.F = _f32(np.eye(dim) + 0.05 * rng.normal(0.0, 1.0, (8, dim, dim)))
+    return s
+
+
+def random_state(scene: Scene, seed: int, c_scale: float = 1.0, f_scale: float = 0.05,
+                 v_scale: float = 0.3) -> Scene:
+    """The same positions with random v, C and F = I + f_scale N(0,1): a generic state
+    for single-step and per-stage checks."""
+    rng = np.random.default_rng(seed)
+    N, d = scene.x.shape
+    return replace(scene, v=_f32(rng.normal(0, v_scale, (N, d))),
+                   C=_f32(rng.normal(0, c_scale, (N, d, d))),
+                   F=_f32(np.eye(d) + f_scale * rng.normal(0, 1, (N, d, d))))
+
+
+REGISTRY = {"c1": c1, "c1d": c1d, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+
+
+def make(name: str, **kw) -> Scene:
+    return REGISTRY[name](**kw)
