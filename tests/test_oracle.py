@@ -389,3 +389,47 @@ def test_error_bits():
     assert orc.step_fwd(inv, _state(inv))[1] & orc.ERR_INVERTED
     nan = _one_particle(2, [8 * dx, 8 * dx], v=[np.nan, 0.0], n=n)
     assert orc.step_fwd(nan, _state(nan))[1] & orc.ERR_NONFINITE
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_mirror_symmetry_with_wall_contact(dim):
+    """As the mirror test, but the particles sit against the low wall of axis 0
+    (their stencils reach the sticky layer), so the mirrored run exercises the
+    high wall: the sticky band must be symmetric under i -> n-1-i."""
+    sc = scenes.fd8(dim, steps=4)
+    n, dx = sc.n_grid, sc.dx
+    x, v, C, F = [a.astype(np.float64) for a in (sc.x, sc.v, sc.C, sc.F)]
+    x[:, 0] += (3.3 * dx) - x[:, 0].min()
+    v[:, 0] = -np.abs(v[:, 0]) - 0.5
+    Sg = np.ones(dim)
+    Sg[0] = -1.0
+    Sm = np.outer(Sg, Sg)
+    xm = x.copy()
+    xm[:, 0] = (n - 1) * dx - x[:, 0]
+    out, _, e1 = orc.run_fwd(sc, sc.steps, orc.pack(x, v, C, F))
+    outm, _, e2 = orc.run_fwd(sc, sc.steps, orc.pack(xm, v * Sg, C * Sm, F * Sm))
+    assert e1 == 0 and e2 == 0
+    xo, vo, Co, Fo = orc.unpack(out, dim)
+    xq, vq, Cq, Fq = orc.unpack(outm, dim)
+    xq[:, 0] = (n - 1) * dx - xq[:, 0]
+    np.testing.assert_allclose(xq, xo, atol=1e-14)
+    np.testing.assert_allclose(vq * Sg, vo, atol=1e-12)
+    np.testing.assert_allclose(Cq * Sm, Co, atol=1e-10)
+    np.testing.assert_allclose(Fq * Sm, Fo, atol=1e-12)
+
+
+def test_sticky_band_width():
+    """Three sticky node layers at each wall: a particle whose stencil spans nodes
+    1..3 (and, mirrored, n-4..n-2) leaves zero velocity on nodes 1, 2 (n-3, n-2)
+    and a non-zero velocity on node 3 (n-4)."""
+    n = 16
+    dx = 1.0 / n
+    for xpos, sticky, free in [(2.0 * dx, (1, 2), 3), ((n - 3.0) * dx, (n - 3, n - 2), n - 4)]:
+        sc = _one_particle(2, [xpos, 8 * dx], v=[0.7, 0.0], n=n)
+        gp, gv, err = orc.grid(sc, _state(sc))
+        assert err == 0
+        m = gp[0, :, 0].reshape(n, n)
+        vx = gv[0, :, 1].reshape(n, n)
+        for i in sticky:
+            assert m[i].sum() > 0 and np.all(vx[i] == 0.0)
+        assert m[free].sum() > 0 and np.any(vx[free] != 0.0)
