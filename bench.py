@@ -1,0 +1,240 @@
+#!/usr/bin/env python
+"""Throughput of the differentiable MLS-MPM hot path on one MI355X.
+
+A bench "step" is one whole trajectory of the hot path on the 3D workload
+(64^3 grid, dx = 1/64, 32768 particles on a jittered 32^3 lattice, neo-Hookean
+E = 20, nu = 0.3, dt = 5e-4, 256 time steps, full tape): sort + 256 fused
+forward launches, mean-height loss and seed, 1 + 256 + 1 reverse launches with
+the grid recomputed. Inputs are synthetic and already resident in HBM when the
+timed region starts. `value` = particles x time steps x trajectories / seconds
+(fwd+bwd particle-steps/s).
+
+Beside it: the roofline figure of the dominant kernel (algorithmic bytes per
+launch over its mean duration, HIP events on the launch stream), the FP64 CPU
+oracle on a bounded sample of the same workload, and the batched 2D workload
+(256 scenes in one launch per step) against 256 per-scene runs.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd particle-steps/s, 3D MLS-MPM 64³ grid; batched vs per-scene launches"
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_c3.json")
+
+
+def _source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1910_00935_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel_name):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    try:
+        with open(PROFILE_TRAFFIC) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != _source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel_name)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def run_c3(args, torch, rt, scenes):
+    sc = scenes.c3()
+    T = sc.steps
+    N = sc.n_particles
+    sim = rt.Simulator.for_scene(sc)
+    params = rt.params_for_scene(sc)
+    init = rt.state_for_scene(sc)
+    tape = sim.tape(T, 0)
+    final = rt.State.empty(3, N)
+    seed = rt.State.empty(3, N)
+    grad = rt.State.zeros(3, N)
+    gE = torch.zeros(1, device="cuda")
+
+    def step():
+        tape.forward(params, init, final)
+        sim.loss_mean(final, sc.loss_axis, sc.loss_sign, seed)
+        tape.backward(params, seed, grad, gE)
+
+    for _ in range(args.warmup):
+        step()
+    flags = sim.check_errors()
+    if flags:
+        raise RuntimeError(f"device error flags {flags}")
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    secs = max(wall, gpu_ms / 1e3)
+    value = N * T * args.steps / secs
+
+    # Per-kernel durations: the same K trajectories again with every launch of
+    # the two step kernels bracketed by HIP events on the launch stream.
+    sim.set_knob("timing", 1)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    from paper_1910_00935_amd import _lib as L
+    fwd_ms, fwd_n = L.mpm_kernel_stats(sim.ctx, L.MPM_KERNEL_FWD)
+    bwd_ms, bwd_n = L.mpm_kernel_stats(sim.ctx, L.MPM_KERNEL_BWD)
+    sim.set_knob("timing", 0)
+    S = 2 * 3 + 2 * 9
+    per = {
+        # Algorithmic bytes per launch (particle state only): forward reads
+        # state s and writes state s+1 (2 S per particle); reverse reads state
+        # s and dL/dstate(s+1) and writes dL/dstate(s) (3 S per particle).
+        "k_fwd": {"ms": fwd_ms / max(fwd_n, 1), "launches": fwd_n, "bytes": 2 * S * 4 * N, "total_ms": fwd_ms},
+        "k_bwd": {"ms": bwd_ms / max(bwd_n, 1), "launches": bwd_n, "bytes": 3 * S * 4 * N, "total_ms": bwd_ms},
+    }
+    dom_name = max(per, key=lambda k: per[k]["total_ms"])
+    dom = per[dom_name]
+    achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
+    roofline = {
+        "bound": "hbm", "kernel": dom_name + "<3>", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(dom_name),
+        "bytes_per_launch": dom["bytes"], "mean_launch_us": round(dom["ms"] * 1e3, 3),
+        "kernels": {k: {"mean_launch_us": round(v["ms"] * 1e3, 3), "launches": v["launches"],
+                        "alg_bytes_per_launch": v["bytes"]} for k, v in per.items()},
+    }
+    return {
+        "value": value, "ms_per_step": secs * 1e3 / args.steps, "N": N, "T": T, "roofline": roofline,
+        "whole_step_hbm_frac": round((5 * S * 4 * N * T * args.steps / secs) / (HBM_PEAK_GBS * 1e9), 4),
+        "gpu_event_ms": gpu_ms, "wall_s": wall,
+    }
+
+
+def run_cpu_baseline(sample_steps):
+    """The FP64 oracle, single-threaded, on the first `sample_steps` steps of the
+    same 3D workload (all 32768 particles): forward, then the reverse pass
+    (which recomputes the forward from its checkpoint)."""
+    import numpy as np  # noqa: F401
+    import oracle as orc
+    from paper_1910_00935_amd import scenes
+    sc = scenes.c3()
+    st = orc.pack(sc.x, sc.v, sc.C, sc.F)
+    t0 = time.perf_counter()
+    sT, _, _ = orc.run_fwd(sc, sample_steps, st)
+    _, seed = orc.loss_mean_pos(sc, sT, sc.loss_axis, sc.loss_sign)
+    orc.run_bwd(sc, sample_steps, sample_steps, st, seed)
+    dt = time.perf_counter() - t0
+    return {"value": sc.n_particles * sample_steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"3D 64^3 workload, all {sc.n_particles} particles, first {sample_steps} of 256 steps, "
+                      f"fwd + reverse, {dt:.1f} s"}
+
+
+def run_batched(args, torch, rt, scenes, n_scenes=256, steps=256):
+    """2D workload of `n_scenes` independent scenes: one context (one launch per
+    step for all scenes) against one context per scene run back to back."""
+    sc = scenes.c5(n_scenes=n_scenes, steps=steps)
+    N = sc.n_particles
+
+    def make(s):
+        sim = rt.Simulator.for_scene(s)
+        p = rt.params_for_scene(s)
+        init = rt.state_for_scene(s)
+        tape = sim.tape(steps, 0)
+        fin = rt.State.empty(2, s.n_particles)
+        seed = rt.State.empty(2, s.n_particles)
+        g = rt.State.zeros(2, s.n_particles)
+        gE = torch.zeros(s.n_scenes, device="cuda")
+
+        def run():
+            tape.forward(p, init, fin)
+            sim.loss_mean(fin, s.loss_axis, s.loss_sign, seed)
+            tape.backward(p, seed, g, gE)
+        return run, sim
+
+    run, sim = make(sc)
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run()
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    per = [make(sc.subset([k])) for k in range(n_scenes)]
+    for r, _ in per:
+        r()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r, _ in per:
+        r()
+    torch.cuda.synchronize()
+    t_per = time.perf_counter() - t0
+    return {"workload": f"2D, {n_scenes} scenes x 64^2 grids, {N} particles (log-uniform 500..8000 per scene), "
+                        f"{steps} steps, fwd+bwd",
+            "batched_particle_steps_per_s": N * steps / t_batched,
+            "per_scene_particle_steps_per_s": N * steps / t_per,
+            "speedup": t_per / t_batched, "batched_ms": t_batched * 1e3, "per_scene_ms": t_per * 1e3}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-sample-steps", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build's path runs on a single MI355X "
+              f"(--gpus {args.gpus} is not supported)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1910_00935_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1910_00935_amd import build
+        build.build()
+    from paper_1910_00935_amd import runtime as rt
+    from paper_1910_00935_amd import scenes
+    torch.cuda.set_device(0)
+    print("[bench] 3D workload", flush=True)
+    c3 = run_c3(args, torch, rt, scenes)
+    out = {
+        "metric": METRIC, "value": round(c3["value"], 1), "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(c3["ms_per_step"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "3D MLS-MPM fwd+bwd: 64^3 grid, dx=1/64, 32768 particles (jittered 32^3 lattice "
+                               "spaced dx/2), neo-Hookean E=20 nu=0.3, dt=5e-4, 256 steps, full tape, "
+                               "loss = mean final height; one bench step = one trajectory",
+                   "particles": c3["N"], "time_steps": c3["T"]},
+        "roofline": c3["roofline"],
+        "whole_step_hbm_frac": c3["whole_step_hbm_frac"],
+    }
+    if not args.no_batched:
+        print("[bench] batched 2D workload", flush=True)
+        out["batched"] = run_batched(args, torch, rt, scenes)
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", flush=True)
+        out["cpu_baseline"] = run_cpu_baseline(args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,236 @@
+/*
+ * mpm.h -- C ABI of the MI355X (gfx950) differentiable MLS-MPM library.
+ *
+ * The library computes the hot path of the differentiable elastic-object
+ * simulator of DiffTaichi (Hu et al., ICLR 2020), Section 4.1: one
+ * moving-least-squares MPM time step -- particle-to-grid scatter of APIC
+ * momentum, mass and neo-Hookean stress, a grid update, and a grid-to-particle
+ * gather that updates v, C, x and F -- and its reverse-mode adjoint, replayed
+ * from a tape with the grid recomputed inside each adjoint step (Appendix D.1)
+ * and with segment checkpoints (Appendix D.2).
+ *
+ * Conventions (all entry points):
+ *   - Every entry point returns an mpm_status; MPM_OK (0) is success.
+ *     Argument errors are detected on the host before any HIP call and leave
+ *     device memory untouched. MPM_E_HIP reports a failed HIP runtime call.
+ *   - All device pointers are owned by the caller (typically torch tensors);
+ *     the library never calls hipMalloc or hipFree. Device buffers must be
+ *     16-byte aligned. Host pointers are read only during the call.
+ *   - Work is enqueued asynchronously on the caller's stream unless stated.
+ *     A context serves one stream at a time and is not thread-safe.
+ *   - Device arithmetic is FP32 (gradient reductions over particles use FP64
+ *     accumulators).
+ *   - Adjoint outputs ACCUMULATE: for a primal f(X) = Y the adjoint takes
+ *     (X, Y*) and adds dL/dX into X* (Section 3, Appendix B). Callers zero the
+ *     gradient buffers they want to read as plain gradients.
+ *   - Particle state (mpm_state) is structure-of-arrays, component-major:
+ *     x[d][N], v[d][N], C[d*d][N], F[d*d][N] (C and F row-major in (a, b)),
+ *     so component c of particle p is at ptr[c * N + p]. N is the total
+ *     particle count of the context; scene k owns particles
+ *     [scene_offsets[k], scene_offsets[k+1]).
+ *   - Device-side faults of the physics (a particle whose 3^d stencil leaves
+ *     the grid, det F <= 0, a non-finite state) set bits of a device error
+ *     word; mpm_check_errors reads and clears it. Such particles are skipped
+ *     by the scatter and keep their state.
+ */
+#ifndef MPM_H_
+#define MPM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mpm_status;
+enum {
+  MPM_OK = 0,
+  MPM_E_ARG = 1,        /* invalid argument (null, out of range, mismatched sizes)          */
+  MPM_E_CAPACITY = 2,   /* bound workspace or tape memory is too small                      */
+  MPM_E_TAPE = 3,       /* tape misuse: backward before forward, different params, unbound  */
+  MPM_E_HIP = 4,        /* a HIP runtime call failed                                        */
+  MPM_E_DOMAIN = 5,     /* device flag: a particle stencil left the grid                    */
+  MPM_E_INVERTED = 6,   /* device flag: det F <= 0                                          */
+  MPM_E_NONFINITE = 7,  /* device flag: non-finite particle state                           */
+  MPM_E_STATE = 8       /* call order: workspace not bound                                  */
+};
+
+/* Device error-word bits reported by mpm_check_errors. */
+#define MPM_FLAG_DOMAIN 1u
+#define MPM_FLAG_INVERTED 2u
+#define MPM_FLAG_NONFINITE 4u
+
+typedef struct mpm_ctx mpm_ctx;
+typedef struct mpm_tape mpm_tape;
+
+/* Simulation description. Section 4.1 names the method (MLS-MPM after
+ * ChainQueen) but no constants; these fields carry them.
+ *   dim           2 or 3.
+ *   n_grid        nodes per axis (>= 2*bound + 3); nodes sit at i*dx.
+ *   bound         sticky band width: a node whose index on any axis is
+ *                 < bound or >= n_grid - bound gets velocity 0.
+ *   dx, dt        cell size and time step.
+ *   gravity       acceleration along axis 1 ("up"), e.g. -9.8.
+ *   n_scenes      independent scenes, each with its own n_grid^dim grid.
+ *   scene_offsets host array [n_scenes + 1], non-decreasing, offsets[0] = 0;
+ *                 N = scene_offsets[n_scenes] >= 1.
+ *   n_actuators   actuator columns (0..16); act_strength sigma_a multiplies
+ *                 the actuation a_k(s) added to the yy Kirchhoff stress.
+ *   flags         reserved, 0. */
+typedef struct {
+  int32_t dim;
+  int32_t n_grid;
+  int32_t bound;
+  float dx;
+  float dt;
+  float gravity;
+  int32_t n_scenes;
+  const int32_t* scene_offsets;
+  int32_t n_actuators;
+  float act_strength;
+  uint32_t flags;
+} mpm_desc;
+
+/* Particle state: device SoA pointers, each component-major with stride N. */
+typedef struct {
+  float* x; /* [dim][N]     */
+  float* v; /* [dim][N]     */
+  float* C; /* [dim*dim][N] */
+  float* F; /* [dim*dim][N] */
+} mpm_state;
+
+/* Material and actuation parameters (device pointers).
+ *   E, nu    [n_scenes] Young's modulus and Poisson ratio, neo-Hookean with
+ *            mu = E / (2 (1 + nu)), lambda = E nu / ((1 + nu)(1 - 2 nu)).
+ *   vol      [n_scenes] initial particle volume V_p.
+ *   rho      [n_scenes] density; particle mass m_p = rho * vol.
+ *   act_id   [N] actuator column of each particle (-1: none) or NULL.
+ *   act      [n_steps][n_actuators] actuation values a_k(s) or NULL. For the
+ *            single-step calls, row `step` is used. */
+typedef struct {
+  const float* E;
+  const float* nu;
+  const float* vol;
+  const float* rho;
+  const int32_t* act_id;
+  const float* act;
+} mpm_params;
+
+/* Gradients with respect to the parameters (device pointers, accumulate).
+ *   E    [n_scenes] dL/dE or NULL.
+ *   act  [n_steps][n_actuators] dL/da_k(s) or NULL. */
+typedef struct {
+  float* E;
+  float* act;
+} mpm_param_grad;
+
+/* Status text (static string). */
+const char* mpm_status_string(mpm_status s);
+
+/* Creates a context for the description. Host-only: validates the fields,
+ * copies scene_offsets and sizes the workspace. MPM_E_ARG on invalid fields. */
+mpm_status mpm_init(const mpm_desc* desc, mpm_ctx** out);
+
+/* Destroys the context (host objects only; never frees caller memory). */
+void mpm_destroy(mpm_ctx* ctx);
+
+/* Bytes of device workspace the context needs (grids, sort buffers, adjoint
+ * scratch, FP64 reduction accumulators, error word); 0 for a null ctx. */
+size_t mpm_workspace_bytes(const mpm_ctx* ctx);
+
+/* Binds caller-owned device workspace of at least mpm_workspace_bytes bytes
+ * (256-byte aligned) and initialises it (synchronously on the null stream).
+ * MPM_E_CAPACITY if too small, MPM_E_ARG if misaligned. */
+mpm_status mpm_bind_workspace(mpm_ctx* ctx, void* dev, size_t bytes);
+
+/* Sets a knob: "block" (threads per workgroup of the per-particle kernels:
+ * 64, 128 or 256); "timing" (0/1: bracket every launch of the two step
+ * kernels with HIP events on the launch stream, for mpm_kernel_stats).
+ * MPM_E_ARG on an unknown key or value. */
+mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value);
+
+/* Step-kernel timing (measurement support, not part of the method): kernel 0
+ * is the forward step kernel, 1 the reverse step kernel. Waits for the
+ * recorded events, returns the summed duration in ms and the launch count
+ * since the previous call for that kernel, and resets them. Requires the
+ * "timing" knob; otherwise returns zeros. */
+#define MPM_KERNEL_FWD 0
+#define MPM_KERNEL_BWD 1
+mpm_status mpm_kernel_stats(mpm_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);
+
+/* One forward step, state `in` (step `step`) -> `out` (step + 1), in the
+ * caller's particle order: clear_grid, compute_actuation (row `step` of
+ * params->act), p2g, grid_op, g2p (Appendix D.1 stage order). `in` and `out`
+ * must not alias (each state is written once: the Global Data Access Rules of
+ * Section 3). */
+mpm_status mpm_step_fwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, const mpm_state* in,
+                        mpm_state* out, void* stream);
+
+/* Adjoint of one step (Appendix D.1): recomputes the grid from `in`, then
+ * replays g2p*, grid_op*, p2g*; given out_grad = dL/d(state step+1) it ADDS
+ * dL/d(state step) into in_grad and dL/dE, dL/da(step) into pg. */
+mpm_status mpm_step_bwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, const mpm_state* in,
+                        const mpm_state* out_grad, mpm_state* in_grad, mpm_param_grad* pg, void* stream);
+
+/* A tape over n_steps steps (Section 3.2: the tape records the step launches
+ * and replays their adjoints in reverse). ckpt_every = 0 or >= n_steps keeps
+ * every state (full tape); 0 < ckpt_every < n_steps keeps states 0, K, 2K, ...
+ * plus a ring of 2K working slots, and recomputes each segment from its
+ * checkpoint during the reverse pass (Appendix D.2). Host-only. */
+mpm_status mpm_tape_create(mpm_ctx* ctx, int32_t n_steps, int32_t ckpt_every, mpm_tape** out);
+
+/* Bytes of device memory the tape needs (state slots + FP64 accumulators). */
+size_t mpm_tape_bytes(const mpm_tape* tape);
+
+/* Binds caller-owned tape memory (>= mpm_tape_bytes, 256-byte aligned). */
+mpm_status mpm_tape_bind(mpm_tape* tape, void* dev, size_t bytes);
+
+/* Destroys the tape's host objects. */
+void mpm_tape_destroy(mpm_tape* tape);
+
+/* Runs n_steps forward steps from `init` (caller order) and writes the final
+ * state to `final` (caller order). Internally particles are sorted by scene
+ * and cell (Morton order) once, at step 0, and the tape keeps sorted states.
+ * Records the parameter pointers for the reverse pass. */
+mpm_status mpm_tape_forward(mpm_tape* tape, const mpm_params* params, const mpm_state* init, mpm_state* final_state,
+                            void* stream);
+
+/* Reverse pass over the recorded trajectory: given final_grad = dL/d(final
+ * state) (caller order), ADDS dL/d(init) into init_grad (caller order) and
+ * dL/dE, dL/da into pg. MPM_E_TAPE if no forward was recorded or if params
+ * differ from the recorded ones. May be called repeatedly after one forward. */
+mpm_status mpm_tape_backward(mpm_tape* tape, const mpm_params* params, const mpm_state* final_grad,
+                             mpm_state* init_grad, mpm_param_grad* pg, void* stream);
+
+/* Loss on a final state (the pattern of the paper's compute_loss kernel):
+ * kind MPM_LOSS_MEAN_POS gives, per scene k, L_k = sign * mean_p x_{p,axis}.
+ * Writes loss_dev[n_scenes] (device, overwritten) and, if seed is non-null,
+ * OVERWRITES every component of *seed with dL/d(final state), where
+ * L = sum_k L_k (so x-seed = sign / N_k on `axis`, zero elsewhere). With
+ * uniform particle mass per scene this is also the centre-of-mass loss. */
+#define MPM_LOSS_MEAN_POS 0
+mpm_status mpm_loss(mpm_ctx* ctx, int32_t kind, int32_t axis, float sign, const mpm_state* final_state,
+                    float* loss_dev, mpm_state* seed, void* stream);
+
+/* Open-loop actuation signal (the controller of the 2D soft robot, Section
+ * 4.1): act[s][k] = tanh(sum_j W[k][j] sin(omega s dt + 2 pi j / n_sin)
+ * + b[k]) for s < n_steps, k < n_actuators (device buffers, act overwritten). */
+mpm_status mpm_actuation(mpm_ctx* ctx, const float* W, const float* b, int32_t n_sin, float omega,
+                         int32_t n_steps, float* act, void* stream);
+
+/* Adjoint of mpm_actuation: ADDS dL/dW [n_actuators][n_sin] and dL/db
+ * [n_actuators] given gact = dL/dact [n_steps][n_actuators]. */
+mpm_status mpm_actuation_bwd(mpm_ctx* ctx, const float* W, const float* b, int32_t n_sin, float omega,
+                             int32_t n_steps, const float* gact, float* gW, float* gb, void* stream);
+
+/* Synchronises `stream`, reads and clears the device error word. *flags gets
+ * the MPM_FLAG_* bits; the return value maps the lowest set bit to
+ * MPM_E_DOMAIN / MPM_E_INVERTED / MPM_E_NONFINITE (MPM_OK if none). */
+mpm_status mpm_check_errors(mpm_ctx* ctx, void* stream, uint32_t* flags);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPM_H_ */

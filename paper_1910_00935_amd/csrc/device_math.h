@@ -1,0 +1,218 @@
+// Device-side math of one MLS-MPM step and its adjoint, FP32, for gfx950.
+//
+// Method (DiffTaichi, Section 4.1: moving-least-squares MPM after ChainQueen;
+// stage order of Appendix D.1): quadratic B-spline weights on the 3^d nodes
+// base .. base+2 with base = floor(x/dx - 1/2); APIC/MLS affine momentum
+// transfer with kappa = 4/dx^2; compressible neo-Hookean Kirchhoff stress
+// tau = mu (F F^T - I) + lambda ln(J) I evaluated with the initial volume;
+// grid update v = P/m + dt g e_1 on interior nodes with mass (sticky band of
+// `bound` nodes, zero elsewhere); grid-to-particle gather of v and
+// C = kappa sum w v delta^T, x' = x + dt v', F' = (I + dt C') F.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpm {
+
+constexpr unsigned kErrDomain = 1u;
+constexpr unsigned kErrInverted = 2u;
+constexpr unsigned kErrNonfinite = 4u;
+constexpr int kMaxAct = 16;
+
+// Component-major SoA view: component c of particle i at p[c * stride + i].
+struct StateRef {
+  float* x;
+  float* v;
+  float* C;
+  float* F;
+  int stride;
+};
+
+template <int D>
+struct PState {
+  float x[D], v[D], C[D][D], F[D][D];
+};
+
+template <int D>
+__device__ __forceinline__ void load_xF(const StateRef& s, int i, PState<D>& p) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) p.x[a] = s.x[a * s.stride + i];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) p.F[a][b] = s.F[(a * D + b) * s.stride + i];
+}
+
+template <int D>
+__device__ __forceinline__ void load_state(const StateRef& s, int i, PState<D>& p) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    p.x[a] = s.x[a * s.stride + i];
+    p.v[a] = s.v[a * s.stride + i];
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      p.C[a][b] = s.C[(a * D + b) * s.stride + i];
+      p.F[a][b] = s.F[(a * D + b) * s.stride + i];
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void store_state(const StateRef& s, int i, const PState<D>& p) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    s.x[a * s.stride + i] = p.x[a];
+    s.v[a * s.stride + i] = p.v[a];
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      s.C[(a * D + b) * s.stride + i] = p.C[a][b];
+      s.F[(a * D + b) * s.stride + i] = p.F[a][b];
+    }
+}
+
+template <int D>
+__device__ __forceinline__ bool state_finite(const PState<D>& p) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int a = 0; a < D; ++a) acc += p.x[a] * 0.0f + p.v[a] * 0.0f;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) acc += p.C[a][b] * 0.0f + p.F[a][b] * 0.0f;
+  return acc == 0.0f;  // NaN or +-inf anywhere makes acc NaN
+}
+
+// Per-particle stencil: base node, fractional offset f = x/dx - base in
+// [0.5, 1.5), the three B-spline pieces N_o(f) and their derivatives dN/df.
+template <int D>
+struct Sten {
+  int base[D];
+  float f[D];
+  float N[D][3];
+  float dN[D][3];
+};
+
+// Returns false when the stencil would leave [0, n) on some axis (or x is not
+// finite); base is then clamped to 0 so that no caller indexes out of bounds.
+template <int D>
+__device__ __forceinline__ bool make_sten(const float (&x)[D], float inv_dx, int n, Sten<D>& st) {
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    float xs = x[a] * inv_dx;
+    float g = xs - 0.5f;
+    bool in = (g >= 0.0f) && (g < float(n - 2));
+    ok = ok && in;
+    int b = in ? int(floorf(g)) : 0;
+    st.base[a] = b;
+    float f = xs - float(b);
+    st.f[a] = f;
+    st.N[a][0] = 0.5f * (1.5f - f) * (1.5f - f);
+    st.N[a][1] = 0.75f - (f - 1.0f) * (f - 1.0f);
+    st.N[a][2] = 0.5f * (f - 0.5f) * (f - 0.5f);
+    st.dN[a][0] = f - 1.5f;
+    st.dN[a][1] = -2.0f * (f - 1.0f);
+    st.dN[a][2] = f - 0.5f;
+  }
+  return ok;
+}
+
+template <int D>
+__device__ __forceinline__ float det(const float (&F)[D][D]) {
+  if constexpr (D == 2) {
+    return F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  } else {
+    return F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+           F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+  }
+}
+
+// cof(F) = det(F) F^{-T}.
+template <int D>
+__device__ __forceinline__ void cofactor(const float (&F)[D][D], float (&K)[D][D]) {
+  if constexpr (D == 2) {
+    K[0][0] = F[1][1];
+    K[0][1] = -F[1][0];
+    K[1][0] = -F[0][1];
+    K[1][1] = F[0][0];
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int a1 = (a + 1) % 3, a2 = (a + 2) % 3, b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+        K[a][b] = F[a1][b1] * F[a2][b2] - F[a1][b2] * F[a2][b1];
+      }
+  }
+}
+
+struct SceneParams {
+  float mass, vol, mu, lam, dmu_dE, dlam_dE;
+};
+
+__device__ __forceinline__ SceneParams scene_params(const float* E, const float* nu, const float* vol,
+                                                    const float* rho, int sc) {
+  SceneParams p;
+  const float e = E[sc], n = nu[sc];
+  p.vol = vol[sc];
+  p.mass = rho[sc] * p.vol;
+  p.dmu_dE = 1.0f / (2.0f * (1.0f + n));
+  p.dlam_dE = n / ((1.0f + n) * (1.0f - 2.0f * n));
+  p.mu = e * p.dmu_dE;
+  p.lam = e * p.dlam_dE;
+  return p;
+}
+
+// Kirchhoff stress and the affine matrix A = m C - dt V kappa tau.
+// Also returns F F^T - I and ln J for the adjoint.
+template <int D>
+__device__ __forceinline__ void affine(const PState<D>& p, const SceneParams& sp, float act_tau, float dt,
+                                       float kappa, float (&A)[D][D], float (&FFtI)[D][D], float& lnJ,
+                                       float& J, unsigned& err) {
+  J = det<D>(p.F);
+  if (J > 0.0f) {
+    lnJ = logf(J);
+  } else {
+    lnJ = 0.0f;
+    err |= kErrInverted;
+  }
+  const float k = dt * sp.vol * kappa;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float s = 0.0f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) s += p.F[a][c] * p.F[b][c];
+      FFtI[a][b] = s - (a == b ? 1.0f : 0.0f);
+      float tau = sp.mu * FFtI[a][b] + (a == b ? sp.lam * lnJ : 0.0f);
+      if (a == 1 && b == 1) tau += act_tau;
+      A[a][b] = sp.mass * p.C[a][b] - k * tau;
+    }
+}
+
+template <int D>
+__device__ __forceinline__ int node_of(const int (&base)[D], int o0, int o1, int o2, int n) {
+  if constexpr (D == 2) {
+    return (base[0] + o0) * n + (base[1] + o1);
+  } else {
+    return ((base[0] + o0) * n + (base[1] + o1)) * n + (base[2] + o2);
+  }
+}
+
+__device__ __forceinline__ bool interior1(int i, int n, int bound) { return i >= bound && i < n - bound; }
+
+// Warp (wave64) sum.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace mpm

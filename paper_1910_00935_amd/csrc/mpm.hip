@@ -1,0 +1,791 @@
+// Host runtime and C ABI of the differentiable MLS-MPM library (gfx950).
+//
+// Owns no device memory: the caller binds a workspace (grids, sort buffers,
+// adjoint partials, FP64 accumulators, error word) and tape memory (state
+// slots). The forward trajectory is one fused launch per step; the reverse is
+// one fused launch per step with the grid recomputed (DiffTaichi Appendix D.1)
+// and, for checkpointed tapes, each segment recomputed from its checkpoint
+// before its steps are reversed (Appendix D.2).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mpm.h"
+#include "step_kernels.h"
+#include "util_kernels.h"
+
+using mpm::BwdArgs;
+using mpm::FwdArgs;
+using mpm::StateRef;
+using mpm::StepConsts;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+// Buffers of the workspace, in order.
+enum Region {
+  R_GRID,      // 10 grids: 0-2 forward, 3-6 reverse primal, 7-9 reverse adjoint
+  R_PARTIAL,   // (d + d^2) x Np floats
+  R_SEED,      // S x Np floats, sorted dL/dstate(T)
+  R_KEYS,      // N uint32
+  R_PERM,      // N int32: sorted index -> caller index
+  R_COUNTS,    // n_keys int32
+  R_START,     // n_keys int32
+  R_BSUMS,     // scan block sums
+  R_SCENE_ID,  // N int32
+  R_ACT_ID,    // N int32, sorted actuator ids
+  R_OFFSETS,   // n_scenes + 1 int32
+  R_GE,        // n_scenes double
+  R_GACT,      // kMaxAct double (single-step adjoint)
+  R_ERR,       // 1 uint32
+  R_COUNT
+};
+
+constexpr int kNumGrids = 10;
+constexpr int kGridF = 0, kGridB = 3, kAdj = 7;
+
+}  // namespace
+
+struct mpm_ctx {
+  int d = 0, n = 0, bound = 0, ns = 0, n_act = 0, N = 0, Np = 0, S = 0;
+  long nodes = 0;
+  float dx = 0, dt = 0, gravity = 0, act_strength = 0;
+  int bits = 0;
+  unsigned cells_per_scene = 0;
+  long n_keys = 0;
+  std::vector<int> offsets;
+  size_t off[R_COUNT] = {}, bytes[R_COUNT] = {};
+  size_t ws_bytes = 0;
+  char* ws = nullptr;
+  int block = 256;
+  // Per-kernel timing (knob "timing"): event pairs around each step-kernel
+  // launch, read back by mpm_kernel_stats.
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  size_t ev_used = 0;
+  double ev_ms[2] = {0.0, 0.0};
+  long ev_count[2] = {0, 0};
+
+  template <class T>
+  T* at(Region r) const {
+    return reinterpret_cast<T*>(ws + off[r]);
+  }
+  float4* grid(int k) const { return at<float4>(R_GRID) + size_t(k) * ns * nodes; }
+  long grid_f4() const { return long(ns) * nodes; }
+  int blocks_for(long n_items) const { return int((n_items + block - 1) / block); }
+};
+
+struct mpm_tape {
+  mpm_ctx* ctx = nullptr;
+  int T = 0, K = 0;
+  bool full = true;
+  int n_ckpt = 0, R = 0, n_slots = 0;
+  size_t slot_floats = 0, off_gact = 0, total = 0;
+  char* mem = nullptr;
+  bool recorded = false;
+  mpm_params rec{};
+  std::vector<int> ring_holds;
+
+  int slot_index(int s) const {
+    if (s == T) return n_ckpt;
+    if (!full && s % K == 0) return s / K;
+    if (full && s == 0) return 0;
+    const int r = full ? (s - 1) : (s % (2 * K));
+    return n_ckpt + 1 + r;
+  }
+  float* slot_base(int s) const {
+    return reinterpret_cast<float*>(mem) + size_t(slot_index(s)) * slot_floats;
+  }
+  StateRef slot(int s) const {
+    const mpm_ctx& c = *ctx;
+    float* b = slot_base(s);
+    const size_t Np = size_t(c.Np);
+    return StateRef{b, b + c.d * Np, b + 2 * c.d * Np, b + (2 * c.d + c.d * c.d) * Np, c.Np};
+  }
+  double* gact() const { return reinterpret_cast<double*>(mem + off_gact); }
+};
+
+namespace {
+
+#define HIP_TRY(expr)                           \
+  do {                                          \
+    if ((expr) != hipSuccess) return MPM_E_HIP; \
+  } while (0)
+
+#define LAUNCH_TRY()                                  \
+  do {                                                \
+    if (hipGetLastError() != hipSuccess) return MPM_E_HIP; \
+  } while (0)
+
+bool state_ok(const mpm_state* s) { return s && s->x && s->v && s->C && s->F; }
+bool params_ok(const mpm_params* p) { return p && p->E && p->nu && p->vol && p->rho; }
+
+StateRef user_ref(const mpm_ctx& c, const mpm_state* s) {
+  return StateRef{s->x, s->v, s->C, s->F, c.N};
+}
+
+StepConsts consts(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
+  StepConsts k;
+  k.N = c.N;
+  k.n = c.n;
+  k.bound = c.bound;
+  k.nodes = int(c.nodes);
+  k.n_act = c.n_act;
+  k.dx = c.dx;
+  k.inv_dx = 1.0f / c.dx;
+  k.dt = c.dt;
+  k.gdt = c.gravity * c.dt;
+  k.kappa = 4.0f / (c.dx * c.dx);
+  k.act_strength = c.act_strength;
+  k.scene_id = c.ns > 1 ? c.at<int>(R_SCENE_ID) : nullptr;
+  k.E = p->E;
+  k.nu = p->nu;
+  k.vol = p->vol;
+  k.rho = p->rho;
+  k.act_id = (c.n_act > 0) ? act_id : nullptr;
+  k.err = c.at<unsigned>(R_ERR);
+  return k;
+}
+
+const float* act_row(const mpm_ctx& c, const mpm_params* p, int s) {
+  return (p->act && c.n_act > 0) ? p->act + size_t(s) * c.n_act : nullptr;
+}
+
+mpm_status zero_f4(const mpm_ctx& c, float4* p, long n, hipStream_t st) {
+  const int blocks = int(std::min<long>((n + 255) / 256, 8192));
+  if (blocks <= 0) return MPM_OK;
+  hipLaunchKernelGGL(mpm::k_zero_f4, dim3(blocks), dim3(256), 0, st, p, n);
+  LAUNCH_TRY();
+  return MPM_OK;
+}
+
+mpm_status zero_f64(double* p, long n, hipStream_t st) {
+  if (n <= 0) return MPM_OK;
+  const int blocks = int(std::min<long>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(mpm::k_zero_f64, dim3(blocks), dim3(256), 0, st, p, n);
+  LAUNCH_TRY();
+  return MPM_OK;
+}
+
+hipEvent_t pool_event(mpm_ctx& c) {
+  if (c.ev_used == c.ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c.ev_pool.push_back(e);
+  }
+  return c.ev_pool[c.ev_used++];
+}
+
+// Brackets one launch with timing events when the "timing" knob is on.
+struct Timed {
+  mpm_ctx& c;
+  int kind;
+  hipStream_t st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  Timed(const mpm_ctx& cc, int k, hipStream_t s) : c(const_cast<mpm_ctx&>(cc)), kind(k), st(s) {
+    if (c.timing) {
+      e0 = pool_event(c);
+      e1 = pool_event(c);
+      if (e0 && e1) hipEventRecord(e0, st);
+    }
+  }
+  ~Timed() {
+    if (e0 && e1) {
+      hipEventRecord(e1, st);
+      c.ev_pending.push_back({kind, {e0, e1}});
+    }
+  }
+};
+
+template <int D>
+mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& a, hipStream_t st) {
+  Timed t(c, 0, st);
+  hipLaunchKernelGGL(mpm::k_fwd<D>, dim3(c.blocks_for(c.N)), dim3(c.block), 0, st, a);
+  LAUNCH_TRY();
+  return MPM_OK;
+}
+
+template <int D>
+mpm_status launch_bwd(const mpm_ctx& c, const BwdArgs& a, hipStream_t st) {
+  Timed t(c, 1, st);
+  hipLaunchKernelGGL(mpm::k_bwd<D>, dim3(c.blocks_for(c.N)), dim3(c.block), 0, st, a);
+  LAUNCH_TRY();
+  return MPM_OK;
+}
+
+mpm_status fwd(const mpm_ctx& c, const FwdArgs& a, hipStream_t st) {
+  return c.d == 2 ? launch_fwd<2>(c, a, st) : launch_fwd<3>(c, a, st);
+}
+mpm_status bwd(const mpm_ctx& c, const BwdArgs& a, hipStream_t st) {
+  return c.d == 2 ? launch_bwd<2>(c, a, st) : launch_bwd<3>(c, a, st);
+}
+
+FwdArgs fwd_args(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
+  FwdArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.k = consts(c, p, act_id);
+  return a;
+}
+
+BwdArgs bwd_args(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
+  BwdArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.k = consts(c, p, act_id);
+  a.partial = c.at<float>(R_PARTIAL);
+  a.pstride = c.Np;
+  return a;
+}
+
+// Sorts particles by (scene, Morton cell) of `st`; writes R_PERM.
+mpm_status sort_particles(const mpm_ctx& c, StateRef st, hipStream_t s) {
+  int* counts = c.at<int>(R_COUNTS);
+  int* start = c.at<int>(R_START);
+  int* bsums = c.at<int>(R_BSUMS);
+  const long nk = c.n_keys;
+  const int zb = int(std::min<long>((nk + 255) / 256, 8192));
+  hipLaunchKernelGGL(mpm::k_zero_i32, dim3(zb), dim3(256), 0, s, counts, nk);
+  LAUNCH_TRY();
+  const int* sid = c.ns > 1 ? c.at<int>(R_SCENE_ID) : nullptr;
+  const int pb = (c.N + 255) / 256;
+  if (c.d == 2)
+    hipLaunchKernelGGL(mpm::k_sort_keys<2>, dim3(pb), dim3(256), 0, s, st, c.N, sid, 1.0f / c.dx, c.n, c.bits,
+                       c.cells_per_scene, c.at<unsigned>(R_KEYS), counts);
+  else
+    hipLaunchKernelGGL(mpm::k_sort_keys<3>, dim3(pb), dim3(256), 0, s, st, c.N, sid, 1.0f / c.dx, c.n, c.bits,
+                       c.cells_per_scene, c.at<unsigned>(R_KEYS), counts);
+  LAUNCH_TRY();
+  const int nb = int((nk + mpm::kScanChunk - 1) / mpm::kScanChunk);
+  hipLaunchKernelGGL(mpm::k_scan_blocks, dim3(nb), dim3(mpm::kScanThreads), 0, s, counts, start, nk, bsums);
+  LAUNCH_TRY();
+  hipLaunchKernelGGL(mpm::k_scan_sums, dim3(1), dim3(mpm::kScanThreads), 0, s, bsums, nb);
+  LAUNCH_TRY();
+  hipLaunchKernelGGL(mpm::k_scan_add, dim3(nb), dim3(256), 0, s, start, nk, bsums);
+  LAUNCH_TRY();
+  hipLaunchKernelGGL(mpm::k_zero_i32, dim3(zb), dim3(256), 0, s, counts, nk);
+  LAUNCH_TRY();
+  hipLaunchKernelGGL(mpm::k_sort_scatter, dim3(pb), dim3(256), 0, s, c.at<unsigned>(R_KEYS), c.N, start, counts,
+                     c.at<int>(R_PERM));
+  LAUNCH_TRY();
+  hipLaunchKernelGGL(mpm::k_sort_fixup, dim3(int((nk + 255) / 256)), dim3(256), 0, s, c.at<int>(R_PERM), start, nk,
+                     c.N);
+  LAUNCH_TRY();
+  return MPM_OK;
+}
+
+mpm_status gather_state(const mpm_ctx& c, StateRef src, StateRef dst, const int* perm, hipStream_t s) {
+  const int pb = (c.N + 255) / 256;
+  if (c.d == 2)
+    hipLaunchKernelGGL(mpm::k_gather_state<2>, dim3(pb), dim3(256), 0, s, src, dst, perm, c.N);
+  else
+    hipLaunchKernelGGL(mpm::k_gather_state<3>, dim3(pb), dim3(256), 0, s, src, dst, perm, c.N);
+  LAUNCH_TRY();
+  return MPM_OK;
+}
+
+mpm_status scatter_state(const mpm_ctx& c, StateRef src, StateRef dst, const int* perm, hipStream_t s) {
+  const int pb = (c.N + 255) / 256;
+  if (c.d == 2)
+    hipLaunchKernelGGL(mpm::k_scatter_state<2>, dim3(pb), dim3(256), 0, s, src, dst, perm, c.N);
+  else
+    hipLaunchKernelGGL(mpm::k_scatter_state<3>, dim3(pb), dim3(256), 0, s, src, dst, perm, c.N);
+  LAUNCH_TRY();
+  return MPM_OK;
+}
+
+#define TRY(expr)                    \
+  do {                               \
+    mpm_status st_ = (expr);         \
+    if (st_ != MPM_OK) return st_;   \
+  } while (0)
+
+// Forward steps t0 .. t1-1 from state t0 (already in its slot), writing
+// states t0+1 .. t1 into their slots, using the three forward grids.
+mpm_status run_forward(mpm_tape& tp, const mpm_params* p, int t0, int t1, hipStream_t s) {
+  const mpm_ctx& c = *tp.ctx;
+  const int* act_id = p->act_id ? c.at<int>(R_ACT_ID) : nullptr;
+  for (int k = 0; k < 3; ++k) TRY(zero_f4(c, c.grid(kGridF + k), c.grid_f4(), s));
+  FwdArgs a = fwd_args(c, p, act_id);
+  a.in = tp.slot(t0);
+  a.grid_out = c.grid(kGridF);
+  a.act_row = act_row(c, p, t0);
+  a.do_p2g = 1;
+  TRY(fwd(c, a, s));
+  for (int t = t0; t < t1; ++t) {
+    const int u = t - t0;
+    FwdArgs b = fwd_args(c, p, act_id);
+    b.in = tp.slot(t);
+    b.out = tp.slot(t + 1);
+    b.grid_in = c.grid(kGridF + u % 3);
+    b.do_g2p = 1;
+    b.do_p2g = (t + 1 < t1) ? 1 : 0;
+    b.grid_out = c.grid(kGridF + (u + 1) % 3);
+    b.act_row = act_row(c, p, t + 1);
+    b.clear = (t + 1 < t1) ? c.grid(kGridF + (u + 2) % 3) : nullptr;
+    b.clear_n = c.grid_f4();
+    TRY(fwd(c, b, s));
+    if (!tp.full && (t + 1) != tp.T && (t + 1) % tp.K != 0) tp.ring_holds[(t + 1) % (2 * tp.K)] = t + 1;
+  }
+  return MPM_OK;
+}
+
+// Makes state `step` resident (recomputes its segment from the checkpoint).
+mpm_status ensure_state(mpm_tape& tp, const mpm_params* p, int step, hipStream_t s) {
+  if (tp.full || step == tp.T || step % tp.K == 0) return MPM_OK;
+  if (tp.ring_holds[step % (2 * tp.K)] == step) return MPM_OK;
+  const int j = step / tp.K;
+  const int t0 = j * tp.K;
+  const int t1 = std::min(t0 + tp.K, tp.T) - 1;  // last state of the segment kept in the ring
+  return run_forward(tp, p, t0, t1, s);
+}
+
+bool same_params(const mpm_params& a, const mpm_params* b) {
+  return a.E == b->E && a.nu == b->nu && a.vol == b->vol && a.rho == b->rho && a.act_id == b->act_id &&
+         a.act == b->act;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mpm_status_string(mpm_status s) {
+  switch (s) {
+    case MPM_OK: return "ok";
+    case MPM_E_ARG: return "invalid argument";
+    case MPM_E_CAPACITY: return "bound memory too small";
+    case MPM_E_TAPE: return "tape misuse (no recorded forward or different parameters)";
+    case MPM_E_HIP: return "HIP runtime error";
+    case MPM_E_DOMAIN: return "a particle stencil left the grid";
+    case MPM_E_INVERTED: return "deformation gradient with det F <= 0";
+    case MPM_E_NONFINITE: return "non-finite particle state";
+    case MPM_E_STATE: return "workspace not bound";
+    default: return "unknown status";
+  }
+}
+
+mpm_status mpm_init(const mpm_desc* desc, mpm_ctx** out) {
+  if (!desc || !out) return MPM_E_ARG;
+  *out = nullptr;
+  const mpm_desc& d = *desc;
+  if (d.dim != 2 && d.dim != 3) return MPM_E_ARG;
+  if (d.bound < 0 || d.n_grid < 2 * d.bound + 3 || d.n_grid > 1024) return MPM_E_ARG;
+  if (!(d.dx > 0.0f) || !(d.dt > 0.0f)) return MPM_E_ARG;
+  if (d.n_scenes < 1 || !d.scene_offsets) return MPM_E_ARG;
+  if (d.n_actuators < 0 || d.n_actuators > mpm::kMaxAct) return MPM_E_ARG;
+  if (d.scene_offsets[0] != 0) return MPM_E_ARG;
+  for (int k = 0; k < d.n_scenes; ++k)
+    if (d.scene_offsets[k + 1] < d.scene_offsets[k]) return MPM_E_ARG;
+  const long Nl = d.scene_offsets[d.n_scenes];
+  if (Nl < 1 || Nl > (1L << 28)) return MPM_E_ARG;
+  long nodes = 1;
+  for (int a = 0; a < d.dim; ++a) nodes *= d.n_grid;
+  if (nodes * long(d.n_scenes) > (1L << 31) / 4) return MPM_E_ARG;
+
+  mpm_ctx* c = new (std::nothrow) mpm_ctx();
+  if (!c) return MPM_E_ARG;
+  c->d = d.dim;
+  c->n = d.n_grid;
+  c->bound = d.bound;
+  c->ns = d.n_scenes;
+  c->n_act = d.n_actuators;
+  c->N = int(Nl);
+  c->Np = int(align_up(size_t(Nl), 64));
+  c->S = 2 * d.dim + 2 * d.dim * d.dim;
+  c->nodes = nodes;
+  c->dx = d.dx;
+  c->dt = d.dt;
+  c->gravity = d.gravity;
+  c->act_strength = d.act_strength;
+  c->offsets.assign(d.scene_offsets, d.scene_offsets + d.n_scenes + 1);
+  int bits = 0;
+  while ((1 << bits) < d.n_grid) ++bits;
+  c->bits = bits;
+  c->cells_per_scene = 1u << (bits * d.dim);
+  c->n_keys = long(c->cells_per_scene) * d.n_scenes;
+  if (c->n_keys > (1L << 30)) {
+    delete c;
+    return MPM_E_ARG;
+  }
+
+  const size_t Np = size_t(c->Np), N = size_t(c->N);
+  c->bytes[R_GRID] = size_t(kNumGrids) * size_t(c->ns) * size_t(nodes) * sizeof(float4);
+  c->bytes[R_PARTIAL] = size_t(d.dim + d.dim * d.dim) * Np * sizeof(float);
+  c->bytes[R_SEED] = size_t(c->S) * Np * sizeof(float);
+  c->bytes[R_KEYS] = N * sizeof(unsigned);
+  c->bytes[R_PERM] = N * sizeof(int);
+  c->bytes[R_COUNTS] = size_t(c->n_keys) * sizeof(int);
+  c->bytes[R_START] = size_t(c->n_keys) * sizeof(int);
+  c->bytes[R_BSUMS] = size_t((c->n_keys + mpm::kScanChunk - 1) / mpm::kScanChunk + 1) * sizeof(int);
+  c->bytes[R_SCENE_ID] = N * sizeof(int);
+  c->bytes[R_ACT_ID] = N * sizeof(int);
+  c->bytes[R_OFFSETS] = size_t(c->ns + 1) * sizeof(int);
+  c->bytes[R_GE] = size_t(c->ns) * sizeof(double);
+  c->bytes[R_GACT] = size_t(mpm::kMaxAct) * sizeof(double);
+  c->bytes[R_ERR] = sizeof(unsigned);
+  size_t o = 0;
+  for (int r = 0; r < R_COUNT; ++r) {
+    c->off[r] = o;
+    o = align_up(o + c->bytes[r]);
+  }
+  c->ws_bytes = o;
+  *out = c;
+  return MPM_OK;
+}
+
+void mpm_destroy(mpm_ctx* ctx) {
+  if (!ctx) return;
+  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+  delete ctx;
+}
+
+size_t mpm_workspace_bytes(const mpm_ctx* ctx) { return ctx ? ctx->ws_bytes : 0; }
+
+mpm_status mpm_bind_workspace(mpm_ctx* ctx, void* dev, size_t bytes) {
+  if (!ctx || !dev) return MPM_E_ARG;
+  if (reinterpret_cast<uintptr_t>(dev) % kAlign != 0) return MPM_E_ARG;
+  if (bytes < ctx->ws_bytes) return MPM_E_CAPACITY;
+  ctx->ws = static_cast<char*>(dev);
+  std::vector<int> sid(size_t(ctx->N));
+  for (int k = 0; k < ctx->ns; ++k)
+    for (int p = ctx->offsets[k]; p < ctx->offsets[k + 1]; ++p) sid[size_t(p)] = k;
+  HIP_TRY(hipMemcpy(ctx->at<int>(R_SCENE_ID), sid.data(), sid.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ctx->at<int>(R_OFFSETS), ctx->offsets.data(), ctx->offsets.size() * sizeof(int),
+                    hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(ctx->at<unsigned>(R_ERR), 0, sizeof(unsigned)));
+  return MPM_OK;
+}
+
+mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value) {
+  if (!ctx || !key) return MPM_E_ARG;
+  const std::string k(key);
+  if (k == "block") {
+    if (value != 64 && value != 128 && value != 256) return MPM_E_ARG;
+    ctx->block = int(value);
+    return MPM_OK;
+  }
+  if (k == "timing") {
+    if (value != 0 && value != 1) return MPM_E_ARG;
+    ctx->timing = value != 0;
+    return MPM_OK;
+  }
+  return MPM_E_ARG;
+}
+
+mpm_status mpm_kernel_stats(mpm_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches) {
+  if (!ctx || kernel < 0 || kernel > 1 || !total_ms || !launches) return MPM_E_ARG;
+  for (auto& p : ctx->ev_pending) {
+    HIP_TRY(hipEventSynchronize(p.second.second));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+    ctx->ev_ms[p.first] += ms;
+    ctx->ev_count[p.first] += 1;
+  }
+  ctx->ev_pending.clear();
+  ctx->ev_used = 0;
+  *total_ms = ctx->ev_ms[kernel];
+  *launches = ctx->ev_count[kernel];
+  ctx->ev_ms[kernel] = 0.0;
+  ctx->ev_count[kernel] = 0;
+  return MPM_OK;
+}
+
+mpm_status mpm_step_fwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, const mpm_state* in, mpm_state* out,
+                        void* stream) {
+  if (!ctx) return MPM_E_ARG;
+  if (!ctx->ws) return MPM_E_STATE;
+  if (!params_ok(params) || !state_ok(in) || !state_ok(out) || step < 0) return MPM_E_ARG;
+  if (in->x == out->x || in->v == out->v || in->C == out->C || in->F == out->F) return MPM_E_ARG;
+  const mpm_ctx& c = *ctx;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float4* g = c.grid(kGridB);
+  TRY(zero_f4(c, g, c.grid_f4(), s));
+  FwdArgs a = fwd_args(c, params, params->act_id);
+  a.in = user_ref(c, in);
+  a.grid_out = g;
+  a.act_row = act_row(c, params, step);
+  a.do_p2g = 1;
+  TRY(fwd(c, a, s));
+  FwdArgs b = fwd_args(c, params, params->act_id);
+  b.in = user_ref(c, in);
+  b.out = user_ref(c, out);
+  b.grid_in = g;
+  b.do_g2p = 1;
+  return fwd(c, b, s);
+}
+
+mpm_status mpm_step_bwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, const mpm_state* in,
+                        const mpm_state* out_grad, mpm_state* in_grad, mpm_param_grad* pg, void* stream) {
+  if (!ctx) return MPM_E_ARG;
+  if (!ctx->ws) return MPM_E_STATE;
+  if (!params_ok(params) || !state_ok(in) || !state_ok(out_grad) || !state_ok(in_grad) || step < 0)
+    return MPM_E_ARG;
+  const mpm_ctx& c = *ctx;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float4* g = c.grid(kGridB);
+  float4* ad = c.grid(kAdj);
+  TRY(zero_f4(c, g, c.grid_f4(), s));
+  TRY(zero_f4(c, ad, c.grid_f4(), s));
+  TRY(zero_f64(c.at<double>(R_GE), c.ns, s));
+  TRY(zero_f64(c.at<double>(R_GACT), mpm::kMaxAct, s));
+  FwdArgs a = fwd_args(c, params, params->act_id);
+  a.in = user_ref(c, in);
+  a.grid_out = g;
+  a.act_row = act_row(c, params, step);
+  a.do_p2g = 1;
+  TRY(fwd(c, a, s));
+  // Seed -> g2p*(step): scatter into the adjoint grid, keep x*, F* partials.
+  BwdArgs b = bwd_args(c, params, params->act_id);
+  b.a_mode = 0;
+  b.seed = user_ref(c, out_grad);
+  b.stB = user_ref(c, in);
+  b.cnext = nullptr;
+  b.gB = g;
+  b.aB = ad;
+  TRY(bwd(c, b, s));
+  // p2g*(step) and output.
+  BwdArgs e = bwd_args(c, params, params->act_id);
+  e.a_mode = 1;
+  e.stA = user_ref(c, in);
+  e.gA = g;
+  e.aA = ad;
+  e.act_rowA = act_row(c, params, step);
+  e.gact_rowA = c.at<double>(R_GACT);
+  e.gE = c.at<double>(R_GE);
+  e.final_out = 1;
+  e.out = user_ref(c, in_grad);
+  e.out_perm = nullptr;
+  TRY(bwd(c, e, s));
+  if (pg && pg->E) {
+    hipLaunchKernelGGL(mpm::k_add_f64_to_f32, dim3((c.ns + 255) / 256), dim3(256), 0, s, c.at<double>(R_GE), pg->E,
+                       c.ns);
+    LAUNCH_TRY();
+  }
+  if (pg && pg->act && c.n_act > 0) {
+    hipLaunchKernelGGL(mpm::k_add_f64_to_f32, dim3(1), dim3(64), 0, s, c.at<double>(R_GACT),
+                       pg->act + size_t(step) * c.n_act, c.n_act);
+    LAUNCH_TRY();
+  }
+  return MPM_OK;
+}
+
+mpm_status mpm_tape_create(mpm_ctx* ctx, int32_t n_steps, int32_t ckpt_every, mpm_tape** out) {
+  if (!ctx || !out || n_steps < 1 || ckpt_every < 0) return MPM_E_ARG;
+  *out = nullptr;
+  mpm_tape* t = new (std::nothrow) mpm_tape();
+  if (!t) return MPM_E_ARG;
+  t->ctx = ctx;
+  t->T = n_steps;
+  t->full = (ckpt_every == 0 || ckpt_every >= n_steps);
+  t->K = t->full ? n_steps : ckpt_every;
+  if (t->full) {
+    t->n_ckpt = 1;
+    t->R = std::max(n_steps - 1, 0);
+  } else {
+    t->n_ckpt = (n_steps - 1) / t->K + 1;
+    t->R = 2 * t->K;
+    t->ring_holds.assign(size_t(t->R), -1);
+  }
+  t->n_slots = t->n_ckpt + 1 + t->R;
+  t->slot_floats = size_t(ctx->S) * size_t(ctx->Np);
+  const size_t slots_bytes = align_up(size_t(t->n_slots) * t->slot_floats * sizeof(float));
+  t->off_gact = slots_bytes;
+  t->total = align_up(slots_bytes + size_t(n_steps) * size_t(std::max(ctx->n_act, 1)) * sizeof(double));
+  *out = t;
+  return MPM_OK;
+}
+
+size_t mpm_tape_bytes(const mpm_tape* tape) { return tape ? tape->total : 0; }
+
+mpm_status mpm_tape_bind(mpm_tape* tape, void* dev, size_t bytes) {
+  if (!tape || !dev) return MPM_E_ARG;
+  if (reinterpret_cast<uintptr_t>(dev) % kAlign != 0) return MPM_E_ARG;
+  if (bytes < tape->total) return MPM_E_CAPACITY;
+  tape->mem = static_cast<char*>(dev);
+  tape->recorded = false;
+  return MPM_OK;
+}
+
+void mpm_tape_destroy(mpm_tape* tape) { delete tape; }
+
+mpm_status mpm_tape_forward(mpm_tape* tape, const mpm_params* params, const mpm_state* init, mpm_state* final_state,
+                            void* stream) {
+  if (!tape || !params_ok(params) || !state_ok(init) || !state_ok(final_state)) return MPM_E_ARG;
+  if (!tape->mem) return MPM_E_TAPE;
+  mpm_ctx& c = *tape->ctx;
+  if (!c.ws) return MPM_E_STATE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  tape->recorded = false;
+  if (!tape->full) std::fill(tape->ring_holds.begin(), tape->ring_holds.end(), -1);
+  const StateRef init_ref = user_ref(c, init);
+  TRY(sort_particles(c, init_ref, s));
+  const int* perm = c.at<int>(R_PERM);
+  TRY(gather_state(c, init_ref, tape->slot(0), perm, s));
+  if (params->act_id && c.n_act > 0) {
+    hipLaunchKernelGGL(mpm::k_gather_i32, dim3((c.N + 255) / 256), dim3(256), 0, s, params->act_id,
+                       c.at<int>(R_ACT_ID), perm, c.N);
+    LAUNCH_TRY();
+  }
+  TRY(run_forward(*tape, params, 0, tape->T, s));
+  TRY(scatter_state(c, tape->slot(tape->T), user_ref(c, final_state), perm, s));
+  tape->rec = *params;
+  tape->recorded = true;
+  return MPM_OK;
+}
+
+mpm_status mpm_tape_backward(mpm_tape* tape, const mpm_params* params, const mpm_state* final_grad,
+                             mpm_state* init_grad, mpm_param_grad* pg, void* stream) {
+  if (!tape || !params_ok(params) || !state_ok(final_grad) || !state_ok(init_grad)) return MPM_E_ARG;
+  if (!tape->mem || !tape->recorded || !same_params(tape->rec, params)) return MPM_E_TAPE;
+  mpm_ctx& c = *tape->ctx;
+  if (!c.ws) return MPM_E_STATE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int T = tape->T;
+  const int* perm = c.at<int>(R_PERM);
+  const int* act_id = params->act_id ? c.at<int>(R_ACT_ID) : nullptr;
+  const size_t Np = size_t(c.Np);
+  float* seedb = c.at<float>(R_SEED);
+  const StateRef seed{seedb, seedb + c.d * Np, seedb + 2 * c.d * Np, seedb + (2 * c.d + c.d * c.d) * Np, c.Np};
+  TRY(gather_state(c, user_ref(c, final_grad), seed, perm, s));
+  TRY(zero_f64(c.at<double>(R_GE), c.ns, s));
+  TRY(zero_f64(tape->gact(), long(T) * std::max(c.n_act, 1), s));
+  for (int k = kGridB; k < kNumGrids; ++k) TRY(zero_f4(c, c.grid(k), c.grid_f4(), s));
+
+  auto gB = [&](int step) { return c.grid(kGridB + step % 4); };
+  auto aB = [&](int step) { return c.grid(kAdj + step % 3); };
+
+  TRY(ensure_state(*tape, params, T - 1, s));
+  {
+    FwdArgs a = fwd_args(c, params, act_id);
+    a.in = tape->slot(T - 1);
+    a.grid_out = gB(T - 1);
+    a.act_row = act_row(c, params, T - 1);
+    a.do_p2g = 1;
+    TRY(fwd(c, a, s));
+  }
+  for (int st = T - 1; st >= 0; --st) {
+    TRY(ensure_state(*tape, params, st, s));
+    if (st >= 1) TRY(ensure_state(*tape, params, st - 1, s));
+    if (st + 1 < T) TRY(ensure_state(*tape, params, st + 1, s));
+    BwdArgs b = bwd_args(c, params, act_id);
+    if (st == T - 1) {
+      b.a_mode = 0;
+      b.seed = seed;
+    } else {
+      b.a_mode = 1;
+      b.stA = tape->slot(st + 1);
+      b.gA = gB(st + 1);
+      b.aA = aB(st + 1);
+      b.act_rowA = act_row(c, params, st + 1);
+      b.gact_rowA = (c.n_act > 0) ? tape->gact() + size_t(st + 1) * c.n_act : nullptr;
+      b.gE = c.at<double>(R_GE);
+    }
+    b.stB = tape->slot(st);
+    const StateRef nx = tape->slot(st + 1);
+    b.cnext = nx.C;
+    b.cnext_stride = nx.stride;
+    b.gB = gB(st);
+    b.aB = aB(st);
+    if (st >= 1) {
+      b.do_c = 1;
+      b.stC = tape->slot(st - 1);
+      b.act_rowC = act_row(c, params, st - 1);
+      b.gC = gB(st - 1);
+    }
+    b.clear0 = gB(st + 2);
+    b.clear0_n = c.grid_f4();
+    b.clear1 = aB(st + 2);
+    b.clear1_n = c.grid_f4();
+    TRY(bwd(c, b, s));
+  }
+  {
+    BwdArgs b = bwd_args(c, params, act_id);
+    b.a_mode = 1;
+    b.stA = tape->slot(0);
+    b.gA = gB(0);
+    b.aA = aB(0);
+    b.act_rowA = act_row(c, params, 0);
+    b.gact_rowA = (c.n_act > 0) ? tape->gact() : nullptr;
+    b.gE = c.at<double>(R_GE);
+    b.final_out = 1;
+    b.out = user_ref(c, init_grad);
+    b.out_perm = perm;
+    TRY(bwd(c, b, s));
+  }
+  if (pg && pg->E) {
+    hipLaunchKernelGGL(mpm::k_add_f64_to_f32, dim3((c.ns + 255) / 256), dim3(256), 0, s, c.at<double>(R_GE), pg->E,
+                       c.ns);
+    LAUNCH_TRY();
+  }
+  if (pg && pg->act && c.n_act > 0) {
+    const int n = T * c.n_act;
+    hipLaunchKernelGGL(mpm::k_add_f64_to_f32, dim3((n + 255) / 256), dim3(256), 0, s, tape->gact(), pg->act, n);
+    LAUNCH_TRY();
+  }
+  return MPM_OK;
+}
+
+mpm_status mpm_loss(mpm_ctx* ctx, int32_t kind, int32_t axis, float sign, const mpm_state* final_state,
+                    float* loss_dev, mpm_state* seed, void* stream) {
+  if (!ctx || kind != MPM_LOSS_MEAN_POS || !state_ok(final_state) || !loss_dev) return MPM_E_ARG;
+  if (axis < 0 || axis >= ctx->d) return MPM_E_ARG;
+  if (seed && !state_ok(seed)) return MPM_E_ARG;
+  if (!ctx->ws) return MPM_E_STATE;
+  const mpm_ctx& c = *ctx;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  StateRef sd{nullptr, nullptr, nullptr, nullptr, c.N};
+  if (seed) sd = user_ref(c, seed);
+  if (c.d == 2)
+    hipLaunchKernelGGL(mpm::k_loss_mean<2>, dim3(c.ns), dim3(256), 0, s, user_ref(c, final_state),
+                       c.at<int>(R_OFFSETS), axis, sign, loss_dev, sd);
+  else
+    hipLaunchKernelGGL(mpm::k_loss_mean<3>, dim3(c.ns), dim3(256), 0, s, user_ref(c, final_state),
+                       c.at<int>(R_OFFSETS), axis, sign, loss_dev, sd);
+  LAUNCH_TRY();
+  return MPM_OK;
+}
+
+mpm_status mpm_actuation(mpm_ctx* ctx, const float* W, const float* b, int32_t n_sin, float omega, int32_t n_steps,
+                         float* act, void* stream) {
+  if (!ctx || !W || !b || !act || n_sin < 1 || n_steps < 1 || ctx->n_act < 1) return MPM_E_ARG;
+  const int n = n_steps * ctx->n_act;
+  hipLaunchKernelGGL(mpm::k_actuation, dim3((n + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream), W, b,
+                     ctx->n_act, n_sin, omega, ctx->dt, n_steps, act);
+  LAUNCH_TRY();
+  return MPM_OK;
+}
+
+mpm_status mpm_actuation_bwd(mpm_ctx* ctx, const float* W, const float* b, int32_t n_sin, float omega,
+                             int32_t n_steps, const float* gact, float* gW, float* gb, void* stream) {
+  if (!ctx || !W || !b || !gact || !gW || !gb || n_sin < 1 || n_steps < 1 || ctx->n_act < 1) return MPM_E_ARG;
+  const int n = ctx->n_act * (n_sin + 1);
+  hipLaunchKernelGGL(mpm::k_actuation_bwd, dim3((n + 63) / 64), dim3(64), 0, static_cast<hipStream_t>(stream), W, b,
+                     ctx->n_act, n_sin, omega, ctx->dt, n_steps, gact, gW, gb);
+  LAUNCH_TRY();
+  return MPM_OK;
+}
+
+mpm_status mpm_check_errors(mpm_ctx* ctx, void* stream, uint32_t* flags) {
+  if (!ctx) return MPM_E_ARG;
+  if (!ctx->ws) return MPM_E_STATE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipStreamSynchronize(s));
+  unsigned v = 0;
+  HIP_TRY(hipMemcpy(&v, ctx->at<unsigned>(R_ERR), sizeof(unsigned), hipMemcpyDeviceToHost));
+  const unsigned zero = 0;
+  HIP_TRY(hipMemcpy(ctx->at<unsigned>(R_ERR), &zero, sizeof(unsigned), hipMemcpyHostToDevice));
+  if (flags) *flags = v;
+  if (v & MPM_FLAG_DOMAIN) return MPM_E_DOMAIN;
+  if (v & MPM_FLAG_INVERTED) return MPM_E_INVERTED;
+  if (v & MPM_FLAG_NONFINITE) return MPM_E_NONFINITE;
+  return MPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,264 @@
+// Support kernels: particle binning (counting sort by scene and Morton cell
+// order), permutation of states between the caller's order and the sorted
+// internal order, the mean-position loss and its seed, the open-loop
+// actuation signal and its adjoint, and buffer clears.
+#pragma once
+
+#include "device_math.h"
+
+namespace mpm {
+
+__global__ void k_zero_f4(float4* p, long n) {
+  const long stride = long(gridDim.x) * blockDim.x;
+  for (long q = long(blockIdx.x) * blockDim.x + threadIdx.x; q < n; q += stride) p[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+__global__ void k_zero_i32(int* p, long n) {
+  const long stride = long(gridDim.x) * blockDim.x;
+  for (long q = long(blockIdx.x) * blockDim.x + threadIdx.x; q < n; q += stride) p[q] = 0;
+}
+
+__global__ void k_zero_f64(double* p, long n) {
+  const long stride = long(gridDim.x) * blockDim.x;
+  for (long q = long(blockIdx.x) * blockDim.x + threadIdx.x; q < n; q += stride) p[q] = 0.0;
+}
+
+// Interleave the bits of cell coordinates (axis 0 most significant).
+template <int D>
+__device__ __forceinline__ unsigned morton(const int (&c)[D], int bits) {
+  unsigned key = 0;
+  for (int b = bits - 1; b >= 0; --b)
+#pragma unroll
+    for (int a = 0; a < D; ++a) key = (key << 1) | ((unsigned(c[a]) >> b) & 1u);
+  return key;
+}
+
+// key[i] = scene * cells_per_scene + morton(cell of x_i), cells clamped into the grid.
+template <int D>
+__global__ void k_sort_keys(StateRef st, int N, const int* scene_id, float inv_dx, int n, int bits,
+                            unsigned cells_per_scene, unsigned* keys, int* counts) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int c[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    float g = st.x[a * st.stride + i] * inv_dx;
+    int ci = (g >= 0.0f) ? (g < float(n - 1) ? int(g) : n - 1) : 0;  // NaN -> 0
+    c[a] = ci;
+  }
+  const int sc = scene_id ? scene_id[i] : 0;
+  const unsigned key = unsigned(sc) * cells_per_scene + morton<D>(c, bits);
+  keys[i] = key;
+  atomicAdd(counts + key, 1);
+}
+
+// Exclusive scan, three passes: per-block scan (kScanItems per thread), scan
+// of the block sums in one workgroup, add of the scanned sums.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanChunk = kScanThreads * kScanItems;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int& total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    int u = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += u;
+    __syncthreads();
+  }
+  total = sh[kScanThreads - 1];
+  const int incl = sh[t];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void k_scan_blocks(const int* in, int* out, long n, int* block_sums) {
+  __shared__ int sh[kScanThreads];
+  const long base = long(blockIdx.x) * kScanChunk + long(threadIdx.x) * kScanItems;
+  int vals[kScanItems];
+  int s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    vals[j] = (base + j < n) ? in[base + j] : 0;
+    s += vals[j];
+  }
+  int total;
+  int run = block_exclusive_scan(s, sh, total);
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += vals[j];
+  }
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_sums(int* sums, int nb) {
+  __shared__ int sh[kScanThreads];
+  int carry = 0;
+  for (int start = 0; start < nb; start += kScanThreads) {
+    const int j = start + int(threadIdx.x);
+    const int v = (j < nb) ? sums[j] : 0;
+    int total;
+    const int ex = block_exclusive_scan(v, sh, total);
+    if (j < nb) sums[j] = ex + carry;
+    carry += total;
+    __syncthreads();
+  }
+}
+
+__global__ void k_scan_add(int* out, long n, const int* sums) {
+  const long base = long(blockIdx.x) * kScanChunk;
+  const int add = sums[blockIdx.x];
+  for (int j = threadIdx.x; j < kScanChunk; j += blockDim.x)
+    if (base + j < n) out[base + j] += add;
+}
+
+// perm[start[key] + rank] = i, with rank taken from a running counter.
+__global__ void k_sort_scatter(const unsigned* keys, int N, const int* start, int* fill, int* perm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const unsigned key = keys[i];
+  const int pos = start[key] + atomicAdd(fill + key, 1);
+  perm[pos] = i;
+}
+
+// Orders each key's run of perm by particle index, so the sorted order does
+// not depend on atomic arrival order.
+__global__ void k_sort_fixup(int* perm, const int* start, long n_keys, int N) {
+  const long key = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (key >= n_keys) return;
+  const int lo = start[key];
+  const int hi = (key + 1 < n_keys) ? start[key + 1] : N;
+  for (int a = lo + 1; a < hi; ++a) {
+    const int v = perm[a];
+    int b = a - 1;
+    while (b >= lo && perm[b] > v) {
+      perm[b + 1] = perm[b];
+      --b;
+    }
+    perm[b + 1] = v;
+  }
+}
+
+// dst[i] = src[perm[i]] for all S components (perm null: identity).
+template <int D>
+__global__ void k_gather_state(StateRef src, StateRef dst, const int* perm, int N) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int j = perm ? perm[i] : i;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    dst.x[c * dst.stride + i] = src.x[c * src.stride + j];
+    dst.v[c * dst.stride + i] = src.v[c * src.stride + j];
+  }
+#pragma unroll
+  for (int c = 0; c < D * D; ++c) {
+    dst.C[c * dst.stride + i] = src.C[c * src.stride + j];
+    dst.F[c * dst.stride + i] = src.F[c * src.stride + j];
+  }
+}
+
+// dst[perm[i]] = src[i].
+template <int D>
+__global__ void k_scatter_state(StateRef src, StateRef dst, const int* perm, int N) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int j = perm ? perm[i] : i;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    dst.x[c * dst.stride + j] = src.x[c * src.stride + i];
+    dst.v[c * dst.stride + j] = src.v[c * src.stride + i];
+  }
+#pragma unroll
+  for (int c = 0; c < D * D; ++c) {
+    dst.C[c * dst.stride + j] = src.C[c * src.stride + i];
+    dst.F[c * dst.stride + j] = src.F[c * src.stride + i];
+  }
+}
+
+__global__ void k_gather_i32(const int* src, int* dst, const int* perm, int N) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  dst[i] = src[perm ? perm[i] : i];
+}
+
+// One workgroup per scene: L_k = sign * mean_p x_{p,axis}; the seed gets
+// sign / N_k on the loss axis of x and zero in every other component.
+template <int D>
+__global__ void k_loss_mean(StateRef fin, const int* offsets, int axis, float sign, float* loss, StateRef seed) {
+  __shared__ double sh[1024 / 64];
+  const int sc = blockIdx.x;
+  const int lo = offsets[sc], hi = offsets[sc + 1];
+  double s = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) s += double(fin.x[axis * fin.stride + i]);
+  s = wave_sum(s);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < nw; ++q) t += sh[q];
+    loss[sc] = (hi > lo) ? float(double(sign) * t / double(hi - lo)) : 0.0f;
+  }
+  if (seed.x) {
+    const float g = (hi > lo) ? sign / float(hi - lo) : 0.0f;
+    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        seed.x[c * seed.stride + i] = (c == axis) ? g : 0.0f;
+        seed.v[c * seed.stride + i] = 0.0f;
+      }
+#pragma unroll
+      for (int c = 0; c < D * D; ++c) {
+        seed.C[c * seed.stride + i] = 0.0f;
+        seed.F[c * seed.stride + i] = 0.0f;
+      }
+    }
+  }
+}
+
+// act[s][k] = tanh(sum_j W[k][j] sin(omega s dt + 2 pi j / n_sin) + b[k]).
+__global__ void k_actuation(const float* W, const float* b, int n_act, int n_sin, float omega, float dt, int T,
+                            float* act) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= T * n_act) return;
+  const int s = q / n_act, kk = q % n_act;
+  const float t = float(s) * dt;
+  float pre = b[kk];
+  for (int j = 0; j < n_sin; ++j) pre += W[kk * n_sin + j] * sinf(omega * t + 6.283185307179586f * float(j) / float(n_sin));
+  act[q] = tanhf(pre);
+}
+
+// gW[k][j] += sum_s gact[s][k] (1 - a^2) sin(...), gb[k] += sum_s gact[s][k] (1 - a^2).
+// One thread per (k, j) pair; j == n_sin is the bias.
+__global__ void k_actuation_bwd(const float* W, const float* b, int n_act, int n_sin, float omega, float dt, int T,
+                                const float* gact, float* gW, float* gb) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_act * (n_sin + 1)) return;
+  const int kk = q / (n_sin + 1), j = q % (n_sin + 1);
+  double acc = 0.0;
+  for (int s = 0; s < T; ++s) {
+    const float t = float(s) * dt;
+    float pre = b[kk];
+    for (int jj = 0; jj < n_sin; ++jj)
+      pre += W[kk * n_sin + jj] * sinf(omega * t + 6.283185307179586f * float(jj) / float(n_sin));
+    const float a = tanhf(pre);
+    const float d = gact[s * n_act + kk] * (1.0f - a * a);
+    const float basis = (j < n_sin) ? sinf(omega * t + 6.283185307179586f * float(j) / float(n_sin)) : 1.0f;
+    acc += double(d) * double(basis);
+  }
+  if (j < n_sin)
+    gW[kk * n_sin + j] += float(acc);
+  else
+    gb[kk] += float(acc);
+}
+
+// dst[i] += float(src[i]) (FP64 accumulators to the caller's FP32 gradients).
+__global__ void k_add_f64_to_f32(const double* src, float* dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] += float(src[i]);
+}
+
+}  // namespace mpm

@@ -1,0 +1,260 @@
+"""Torch-facing runtime over the C ABI: contexts, states, tapes, and a
+``torch.autograd.Function`` over whole trajectories.
+
+PyTorch only provides device memory (workspace, tape, states) and the stream;
+all simulation work is in the HIP library. States are component-major
+tensors: ``x, v`` of shape (d, N) and ``C, F`` of shape (d, d, N), float32,
+contiguous, on the GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def _dev_bytes(nbytes: int, device) -> torch.Tensor:
+    # The caching allocator returns blocks aligned to at least 512 bytes.
+    t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+@dataclass
+class State:
+    """Particle state, component-major: x, v (d, N); C, F (d, d, N)."""
+    x: torch.Tensor
+    v: torch.Tensor
+    C: torch.Tensor
+    F: torch.Tensor
+
+    def c(self) -> L.mpm_state:
+        for t in (self.x, self.v, self.C, self.F):
+            assert t.is_contiguous() and t.dtype == torch.float32 and t.is_cuda
+        return L.mpm_state(self.x.data_ptr(), self.v.data_ptr(), self.C.data_ptr(), self.F.data_ptr())
+
+    @staticmethod
+    def empty(dim, N, device="cuda") -> "State":
+        return State(torch.empty(dim, N, device=device), torch.empty(dim, N, device=device),
+                     torch.empty(dim, dim, N, device=device), torch.empty(dim, dim, N, device=device))
+
+    @staticmethod
+    def zeros(dim, N, device="cuda") -> "State":
+        return State(torch.zeros(dim, N, device=device), torch.zeros(dim, N, device=device),
+                     torch.zeros(dim, dim, N, device=device), torch.zeros(dim, dim, N, device=device))
+
+    @staticmethod
+    def from_particle_major(x, v, C, F, device="cuda") -> "State":
+        """From (N,d), (N,d), (N,d,d), (N,d,d) arrays (NumPy or torch)."""
+        def t(a):
+            return torch.as_tensor(np.asarray(a, dtype=np.float32) if not torch.is_tensor(a) else a,
+                                   dtype=torch.float32)
+        x, v, C, F = t(x), t(v), t(C), t(F)
+        return State(x.t().contiguous().to(device), v.t().contiguous().to(device),
+                     C.permute(1, 2, 0).contiguous().to(device), F.permute(1, 2, 0).contiguous().to(device))
+
+    def to_particle_major(self):
+        """(N,d), (N,d), (N,d,d), (N,d,d) float64 NumPy arrays."""
+        def n(a):
+            return a.detach().cpu().numpy().astype(np.float64)
+        return (n(self.x).T.copy(), n(self.v).T.copy(), np.transpose(n(self.C), (2, 0, 1)).copy(),
+                np.transpose(n(self.F), (2, 0, 1)).copy())
+
+    def tensors(self):
+        return self.x, self.v, self.C, self.F
+
+
+@dataclass
+class Params:
+    E: torch.Tensor
+    nu: torch.Tensor
+    vol: torch.Tensor
+    rho: torch.Tensor
+    act_id: Optional[torch.Tensor] = None
+    act: Optional[torch.Tensor] = None
+
+    def c(self) -> L.mpm_params:
+        return L.mpm_params(_ptr(self.E), _ptr(self.nu), _ptr(self.vol), _ptr(self.rho), _ptr(self.act_id),
+                            _ptr(self.act))
+
+
+class Simulator:
+    """One context: a description (grid, time step, scenes) plus bound workspace."""
+
+    def __init__(self, dim, n_grid, dx, dt, scene_offsets, gravity=-9.8, bound=3, n_actuators=0,
+                 act_strength=0.0, device="cuda", knobs: Optional[dict] = None):
+        self.dim, self.n_grid, self.dx, self.dt = int(dim), int(n_grid), float(dx), float(dt)
+        self.offsets = np.ascontiguousarray(scene_offsets, dtype=np.int32)
+        self.n_scenes = len(self.offsets) - 1
+        self.N = int(self.offsets[-1])
+        self.n_act = int(n_actuators)
+        self.device = device
+        self._off_c = self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        desc = L.mpm_desc(self.dim, self.n_grid, int(bound), self.dx, self.dt, float(gravity), self.n_scenes,
+                          self._off_c, self.n_act, float(act_strength), 0)
+        self.ctx = L.mpm_init(desc)
+        self.workspace = _dev_bytes(L.mpm_workspace_bytes(self.ctx), device)
+        L.mpm_bind_workspace(self.ctx, self.workspace.data_ptr(), self.workspace.numel())
+        for k, v in (knobs or {}).items():
+            L.mpm_set_knob(self.ctx, k, v)
+
+    @staticmethod
+    def for_scene(scene, device="cuda", knobs=None) -> "Simulator":
+        return Simulator(scene.dim, scene.n_grid, scene.dx, scene.dt, scene.offsets, gravity=scene.gravity,
+                         bound=scene.bound, n_actuators=scene.n_act, act_strength=scene.act_strength,
+                         device=device, knobs=knobs)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            L.mpm_destroy(ctx)
+            self.ctx = None
+
+    def set_knob(self, key, value):
+        L.mpm_set_knob(self.ctx, key, value)
+
+    # Single steps (caller particle order).
+    def step_fwd(self, params: Params, step: int, s_in: State, s_out: State):
+        L.mpm_step_fwd(self.ctx, params.c(), step, s_in.c(), s_out.c(), _stream())
+
+    def step_bwd(self, params: Params, step: int, s_in: State, out_grad: State, in_grad: State,
+                 gE: Optional[torch.Tensor] = None, gact: Optional[torch.Tensor] = None):
+        pg = L.mpm_param_grad(_ptr(gE), _ptr(gact))
+        L.mpm_step_bwd(self.ctx, params.c(), step, s_in.c(), out_grad.c(), in_grad.c(), pg, _stream())
+
+    def tape(self, n_steps: int, ckpt_every: int = 0) -> "Tape":
+        return Tape(self, n_steps, ckpt_every)
+
+    def loss_mean(self, final: State, axis: int, sign: float = 1.0, seed: Optional[State] = None):
+        loss = torch.empty(self.n_scenes, device=self.device)
+        L.mpm_loss(self.ctx, L.MPM_LOSS_MEAN_POS, axis, sign, final.c(), loss.data_ptr(),
+                   None if seed is None else seed.c(), _stream())
+        return loss
+
+    def actuation(self, W: torch.Tensor, b: torch.Tensor, omega: float, n_steps: int) -> torch.Tensor:
+        act = torch.empty(n_steps, self.n_act, device=self.device)
+        L.mpm_actuation(self.ctx, W.data_ptr(), b.data_ptr(), W.shape[1], omega, n_steps, act.data_ptr(), _stream())
+        return act
+
+    def actuation_bwd(self, W, b, omega, n_steps, gact, gW, gb):
+        L.mpm_actuation_bwd(self.ctx, W.data_ptr(), b.data_ptr(), W.shape[1], omega, n_steps, gact.data_ptr(),
+                            gW.data_ptr(), gb.data_ptr(), _stream())
+
+    def check_errors(self):
+        """Synchronises and returns the device error flags (MPM_FLAG_* bits)."""
+        st, flags = L.mpm_check_errors(self.ctx, _stream())
+        return flags
+
+
+class Tape:
+    """Trajectory tape (full, or checkpointed every `ckpt_every` steps)."""
+
+    def __init__(self, sim: Simulator, n_steps: int, ckpt_every: int = 0):
+        self.sim = sim
+        self.n_steps = int(n_steps)
+        self.ckpt_every = int(ckpt_every)
+        self.h = L.mpm_tape_create(sim.ctx, self.n_steps, self.ckpt_every)
+        self.nbytes = L.mpm_tape_bytes(self.h)
+        self.mem = _dev_bytes(self.nbytes, sim.device)
+        L.mpm_tape_bind(self.h, self.mem.data_ptr(), self.nbytes)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            L.mpm_tape_destroy(h)
+            self.h = None
+
+    def forward(self, params: Params, init: State, final: State):
+        L.mpm_tape_forward(self.h, params.c(), init.c(), final.c(), _stream())
+
+    def backward(self, params: Params, final_grad: State, init_grad: State, gE: Optional[torch.Tensor] = None,
+                 gact: Optional[torch.Tensor] = None):
+        pg = L.mpm_param_grad(_ptr(gE), _ptr(gact))
+        L.mpm_tape_backward(self.h, params.c(), final_grad.c(), init_grad.c(), pg, _stream())
+
+
+def params_for_scene(scene, device="cuda", act: Optional[torch.Tensor] = None) -> Params:
+    def f(a):
+        return torch.as_tensor(np.asarray(a, np.float32), device=device)
+    act_id = None
+    if scene.act_id is not None:
+        act_id = torch.as_tensor(np.asarray(scene.act_id, np.int32), device=device)
+    return Params(f(scene.E), f(scene.nu), f(scene.vol), f(scene.rho), act_id, act)
+
+
+def state_for_scene(scene, device="cuda") -> State:
+    return State.from_particle_major(scene.x, scene.v, scene.C, scene.F, device=device)
+
+
+class MPMTrajectory(torch.autograd.Function):
+    """Differentiable trajectory: (x0, v0, C0, F0, E, act) -> (xT, vT, CT, FT).
+
+    The forward runs the tape; the backward replays it in reverse (with
+    segment recompute when the tape is checkpointed) and returns gradients for
+    the initial state, E and the actuation table."""
+
+    @staticmethod
+    def forward(ctx, tape: Tape, x0, v0, C0, F0, E, nu, vol, rho, act_id, act):
+        sim = tape.sim
+        params = Params(E.detach().contiguous(), nu.detach().contiguous(), vol.detach().contiguous(),
+                        rho.detach().contiguous(), act_id, None if act is None else act.detach().contiguous())
+        init = State(x0.detach().contiguous(), v0.detach().contiguous(), C0.detach().contiguous(),
+                     F0.detach().contiguous())
+        final = State.empty(sim.dim, sim.N, sim.device)
+        tape.forward(params, init, final)
+        ctx.tape = tape
+        ctx.params = params
+        ctx.init = init
+        ctx.has_act = act is not None
+        return final.x, final.v, final.C, final.F
+
+    @staticmethod
+    def backward(ctx, gx, gv, gC, gF):
+        tape, sim = ctx.tape, ctx.tape.sim
+
+        def z(g, like):
+            return torch.zeros_like(like) if g is None else g.contiguous()
+
+        fg = State(z(gx, ctx.init.x), z(gv, ctx.init.v), z(gC, ctx.init.C), z(gF, ctx.init.F))
+        ig = State.zeros(sim.dim, sim.N, sim.device)
+        gE = torch.zeros_like(ctx.params.E)
+        gact = torch.zeros_like(ctx.params.act) if ctx.has_act else None
+        tape.backward(ctx.params, fg, ig, gE, gact)
+        return (None, ig.x, ig.v, ig.C, ig.F, gE, None, None, None, None, gact)
+
+
+class Actuation(torch.autograd.Function):
+    """a[s, k] = tanh(sum_j W[k, j] sin(omega s dt + 2 pi j / n_sin) + b[k]) on the GPU."""
+
+    @staticmethod
+    def forward(ctx, sim: Simulator, W, b, omega: float, n_steps: int):
+        W = W.detach().contiguous()
+        b = b.detach().contiguous()
+        ctx.sim, ctx.W, ctx.b, ctx.omega, ctx.n_steps = sim, W, b, omega, n_steps
+        return sim.actuation(W, b, omega, n_steps)
+
+    @staticmethod
+    def backward(ctx, gact):
+        gW = torch.zeros_like(ctx.W)
+        gb = torch.zeros_like(ctx.b)
+        ctx.sim.actuation_bwd(ctx.W, ctx.b, ctx.omega, ctx.n_steps, gact.contiguous(), gW, gb)
+        return None, gW, gb, None, None
+
+
+def trajectory(tape: Tape, init: State, params: Params, act: Optional[torch.Tensor] = None):
+    """Differentiable final state of `tape.n_steps` steps."""
+    return MPMTrajectory.apply(tape, init.x, init.v, init.C, init.F, params.E, params.nu, params.vol, params.rho,
+                               params.act_id, act)

@@ -1,0 +1,120 @@
+"""The C-ABI library loads, exports every symbol its header declares, and its
+host-only entry points (description checks, workspace and tape sizing, knobs,
+status strings) behave as documented. No GPU call is made here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1910_00935_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpm.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(mpm_[a-z_0-9]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert len(names) >= 18, names
+    lib = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # The binding covers exactly the declared entry points.
+    assert sorted(L._SIGNATURES) == names
+
+
+def _desc(dim=3, n=64, ns=1, N=1000, bound=3, n_act=0, offsets=None):
+    off = np.array(offsets if offsets is not None else np.linspace(0, N, ns + 1).astype(int), np.int32)
+    d = L.mpm_desc(dim, n, bound, 1.0 / n, 1e-3, -9.8, len(off) - 1,
+                   off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_act, 0.0, 0)
+    return d, off
+
+
+def _init_status(**kw):
+    d, off = _desc(**kw)
+    h = ctypes.c_void_p()
+    st = L.lib().mpm_init(ctypes.byref(d), ctypes.byref(h))
+    if st == 0:
+        L.lib().mpm_destroy(h)
+    return st
+
+
+def test_init_validates_description():
+    assert _init_status() == L.MPM_OK
+    assert _init_status(dim=4) == L.MPM_E_ARG
+    assert _init_status(dim=1) == L.MPM_E_ARG
+    assert _init_status(n=8, bound=3) == L.MPM_E_ARG      # n < 2*bound + 3
+    assert _init_status(n=9, bound=3) == L.MPM_OK
+    assert _init_status(offsets=[0, 10, 5]) == L.MPM_E_ARG  # decreasing offsets
+    assert _init_status(offsets=[3, 10]) == L.MPM_E_ARG     # offsets[0] != 0
+    assert _init_status(offsets=[0, 0]) == L.MPM_E_ARG      # no particles
+    assert _init_status(n_act=17) == L.MPM_E_ARG
+    h = ctypes.c_void_p()
+    assert L.lib().mpm_init(None, ctypes.byref(h)) == L.MPM_E_ARG
+
+
+def test_workspace_and_tape_sizes():
+    d, off = _desc(dim=3, n=64, N=32768)
+    ctx = L.mpm_init(d)
+    try:
+        ws = L.mpm_workspace_bytes(ctx)
+        grid_bytes = 10 * 64 ** 3 * 16
+        assert grid_bytes < ws < grid_bytes + 32 * 1024 * 1024
+        full = L.mpm_tape_create(ctx, 256, 0)
+        slot = 24 * 32768 * 4
+        assert L.mpm_tape_bytes(full) >= 257 * slot
+        ck = L.mpm_tape_create(ctx, 1024, 64)
+        # 16 checkpoints + final + 2K ring slots.
+        assert 145 * slot <= L.mpm_tape_bytes(ck) < 146 * slot + (1 << 20)
+        for t in (full, ck):
+            L.mpm_tape_destroy(t)
+        bad = ctypes.c_void_p()
+        assert L.lib().mpm_tape_create(ctx, 0, 0, ctypes.byref(bad)) == L.MPM_E_ARG
+        assert L.lib().mpm_tape_create(ctx, 10, -1, ctypes.byref(bad)) == L.MPM_E_ARG
+        # Binding too little memory or misaligned memory is refused before any device access.
+        assert L.lib().mpm_bind_workspace(ctx, ctypes.c_void_p(4096), ctypes.c_size_t(ws - 1)) == L.MPM_E_CAPACITY
+        assert L.lib().mpm_bind_workspace(ctx, ctypes.c_void_p(4096 + 16), ctypes.c_size_t(ws)) == L.MPM_E_ARG
+    finally:
+        L.mpm_destroy(ctx)
+
+
+def test_calls_before_binding_are_refused():
+    d, off = _desc(dim=2, n=64, N=100)
+    ctx = L.mpm_init(d)
+    try:
+        p = L.mpm_params(1, 1, 1, 1, None, None)
+        s = L.mpm_state(1, 1, 1, 1)
+        s2 = L.mpm_state(2, 2, 2, 2)
+        st = L.lib().mpm_step_fwd(ctx, ctypes.byref(p), 0, ctypes.byref(s), ctypes.byref(s2), None)
+        assert st == L.MPM_E_STATE
+        # Aliased in/out is refused (each state is written once).
+        st = L.lib().mpm_step_fwd(ctx, ctypes.byref(p), 0, ctypes.byref(s), ctypes.byref(s), None)
+        assert st in (L.MPM_E_STATE, L.MPM_E_ARG)
+        tape = L.mpm_tape_create(ctx, 4, 0)
+        st = L.lib().mpm_tape_backward(tape, ctypes.byref(p), ctypes.byref(s), ctypes.byref(s2), None, None)
+        assert st == L.MPM_E_TAPE  # no memory bound, nothing recorded
+        L.mpm_tape_destroy(tape)
+    finally:
+        L.mpm_destroy(ctx)
+
+
+def test_knobs_and_status_strings():
+    d, off = _desc(dim=2, n=64, N=100)
+    ctx = L.mpm_init(d)
+    try:
+        L.mpm_set_knob(ctx, "block", 128)
+        assert L.lib().mpm_set_knob(ctx, b"block", 100) == L.MPM_E_ARG
+        assert L.lib().mpm_set_knob(ctx, b"nope", 1) == L.MPM_E_ARG
+    finally:
+        L.mpm_destroy(ctx)
+    for code in range(9):
+        assert L.status_string(code) and L.status_string(code) != "unknown status"
+    assert L.status_string(99) == "unknown status"
