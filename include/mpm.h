@@ -145,7 +145,8 @@ size_t mpm_workspace_bytes(const mpm_ctx* ctx);
 mpm_status mpm_bind_workspace(mpm_ctx* ctx, void* dev, size_t bytes);
 
 /* Sets a knob: "block" (threads per workgroup of the per-particle kernels:
- * 64, 128 or 256); "timing" (0/1: bracket every launch of the two step
+ * 64, 128 or 256); "lds" (0/1, default 1: stage each workgroup's stencil
+ * footprint in LDS when it fits, else use global memory directly); "timing" (0/1: bracket every launch of the two step
  * kernels with HIP events on the launch stream, for mpm_kernel_stats).
  * MPM_E_ARG on an unknown key or value. */
 mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value);

@@ -92,7 +92,7 @@ __device__ __forceinline__ bool state_finite(const PState<D>& p) {
 // [0.5, 1.5), the three B-spline pieces N_o(f) and their derivatives dN/df.
 template <int D>
 struct Sten {
-  int base[D];
+  int base[D] = {};
   float f[D];
   float N[D][3];
   float dN[D][3];

@@ -66,6 +66,7 @@ struct mpm_ctx {
   size_t ws_bytes = 0;
   char* ws = nullptr;
   int block = 256;
+  int lds = 1;
   // Per-kernel timing (knob "timing"): event pairs around each step-kernel
   // launch, read back by mpm_kernel_stats.
   bool timing = false;
@@ -146,6 +147,7 @@ StepConsts consts(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
   k.gdt = c.gravity * c.dt;
   k.kappa = 4.0f / (c.dx * c.dx);
   k.act_strength = c.act_strength;
+  k.lds = c.lds;
   k.scene_id = c.ns > 1 ? c.at<int>(R_SCENE_ID) : nullptr;
   k.E = p->E;
   k.nu = p->nu;
@@ -195,14 +197,11 @@ struct Timed {
     if (c.timing) {
       e0 = pool_event(c);
       e1 = pool_event(c);
-      if (e0 && e1) hipEventRecord(e0, st);
+      if (e0 && e1 && hipEventRecord(e0, st) != hipSuccess) e0 = e1 = nullptr;
     }
   }
   ~Timed() {
-    if (e0 && e1) {
-      hipEventRecord(e1, st);
-      c.ev_pending.push_back({kind, {e0, e1}});
-    }
+    if (e0 && e1 && hipEventRecord(e1, st) == hipSuccess) c.ev_pending.push_back({kind, {e0, e1}});
   }
 };
 
@@ -442,7 +441,7 @@ mpm_status mpm_init(const mpm_desc* desc, mpm_ctx** out) {
 
 void mpm_destroy(mpm_ctx* ctx) {
   if (!ctx) return;
-  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -469,6 +468,11 @@ mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value) {
   if (k == "block") {
     if (value != 64 && value != 128 && value != 256) return MPM_E_ARG;
     ctx->block = int(value);
+    return MPM_OK;
+  }
+  if (k == "lds") {
+    if (value != 0 && value != 1) return MPM_E_ARG;
+    ctx->lds = int(value);
     return MPM_OK;
   }
   if (k == "timing") {

@@ -14,13 +14,25 @@
 //
 // Grids are dense per scene, one float4 per node: (m, P_0, P_1, P_2) for the
 // primal (P = momentum; v is formed at gather time), (v*_0, v*_1, v*_2, -) for
-// the adjoint. Scatters use hardware FP32 atomics; per-scene dL/dE and
-// per-actuator dL/da are reduced per wavefront and added in FP64.
+// the adjoint.
+//
+// LDS staging: particles are sorted by cell (Morton order), so the stencils of
+// one workgroup cover a small box of nodes. Each phase computes that box
+// (block-wide min/max of the stencil bases); when it fits kTileMax nodes and
+// the workgroup holds one scene, gathers read the box once into LDS and
+// scatters accumulate in LDS (ds_add_f32) and flush each non-zero node to HBM
+// with one hardware FP32 atomic per component. Otherwise the phase reads and
+// scatters global memory directly. Per-scene dL/dE and per-actuator dL/da are
+// reduced per wavefront and added in FP64.
 #pragma once
+
+#include <climits>
 
 #include "device_math.h"
 
 namespace mpm {
+
+constexpr int kTileMax = 512;  // nodes per LDS tile (float4 each)
 
 struct StepConsts {
   int N;          // particles
@@ -28,6 +40,7 @@ struct StepConsts {
   int bound;      // sticky band width
   int nodes;      // n^d, nodes per scene
   int n_act;      // actuator columns
+  int lds;        // 1: stage gathers and scatters in LDS when the box fits
   float dx, inv_dx, dt, gdt, kappa, act_strength;
   const int* scene_id;  // [N] scene of each particle, or null (one scene)
   const float* E;
@@ -146,46 +159,172 @@ __device__ __forceinline__ void zero_range(float4* p, long n) {
 __device__ __forceinline__ void atomic_add_f32(float* p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add_f64(double* p, double v) { unsafeAtomicAdd(p, v); }
 
-// p2g of one particle into its scene's grid.
+// ---------------------------------------------------------------------------
+// LDS tiles
+// ---------------------------------------------------------------------------
 template <int D>
-__device__ __forceinline__ void p2g_particle(const StepConsts& k, int i, int sc, const PState<D>& p,
-                                             const float* act_row, float4* grid, unsigned& err) {
-  Sten<D> st;
-  if (!state_finite<D>(p)) {
-    err |= kErrNonfinite;
-    return;
+struct Tile {
+  int lo[D];
+  int ext[D];
+  int n;
+  bool on;
+};
+
+// Node addressing: a box of the scene's grid staged in LDS (L = true), or the
+// scene's global grid.
+template <int D, bool L>
+struct Nodes {
+  float4* p;
+  int lo[D], ext[D];
+  int n;
+  __device__ __forceinline__ int idx(const Sten<D>& st, int o0, int o1, int o2) const {
+    if constexpr (L) {
+      if constexpr (D == 2) {
+        return (st.base[0] + o0 - lo[0]) * ext[1] + (st.base[1] + o1 - lo[1]);
+      } else {
+        return ((st.base[0] + o0 - lo[0]) * ext[1] + (st.base[1] + o1 - lo[1])) * ext[2] + (st.base[2] + o2 - lo[2]);
+      }
+    } else {
+      return node_of<D>(st.base, o0, o1, o2, n);
+    }
   }
-  if (!make_sten<D>(p.x, k.inv_dx, k.n, st)) {
-    err |= kErrDomain;
-    return;
+  __device__ __forceinline__ float4 get(const Sten<D>& st, int o0, int o1, int o2) const {
+    return p[idx(st, o0, o1, o2)];
   }
-  const SceneParams sp = scene_params(k.E, k.nu, k.vol, k.rho, sc);
-  float act_tau = 0.0f;
-  if (act_row && k.act_id) {
-    const int aid = k.act_id[i];
-    if (aid >= 0) act_tau = k.act_strength * act_row[aid];
+  __device__ __forceinline__ float* at(const Sten<D>& st, int o0, int o1, int o2) const {
+    return reinterpret_cast<float*>(p + idx(st, o0, o1, o2));
   }
-  float A[D][D], FFtI[D][D], lnJ, J;
-  affine<D>(p, sp, act_tau, k.dt, k.kappa, A, FFtI, lnJ, J, err);
-  float mv[D];
+};
+
+template <int D>
+__device__ __forceinline__ Nodes<D, true> lds_nodes(float4* tile, const Tile<D>& T) {
+  Nodes<D, true> a;
+  a.p = tile;
 #pragma unroll
-  for (int a = 0; a < D; ++a) mv[a] = sp.mass * p.v[a];
-  float4* g = grid + long(sc) * k.nodes;
-  for_nodes<D>([&](int o0, int o1, int o2) {
-    const float w = wgt<D>(st, o0, o1, o2);
-    float dl[D];
-    delta<D>(st, o0, o1, o2, k.dx, dl);
-    float* node = reinterpret_cast<float*>(g + node_of<D>(st.base, o0, o1, o2, k.n));
-    atomic_add_f32(node, w * sp.mass);
+  for (int q = 0; q < D; ++q) {
+    a.lo[q] = T.lo[q];
+    a.ext[q] = T.ext[q];
+  }
+  a.n = 0;
+  return a;
+}
+
+template <int D>
+__device__ __forceinline__ Nodes<D, false> global_nodes(const float4* g, int n) {
+  Nodes<D, false> a;
+  a.p = const_cast<float4*>(g);
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    a.lo[q] = 0;
+    a.ext[q] = 0;
+  }
+  a.n = n;
+  return a;
+}
+
+// True when every particle of this workgroup belongs to one scene.
+__device__ __forceinline__ bool block_one_scene(const StepConsts& k) {
+  if (!k.scene_id) return true;
+  const int first = blockIdx.x * blockDim.x;
+  const int last = min(first + int(blockDim.x), k.N) - 1;
+  return k.scene_id[first] == k.scene_id[last];
+}
+
+// Block-wide box of the stencil bases of the valid lanes (all threads call).
+template <int D>
+__device__ Tile<D> block_tile(bool valid, const int (&base)[D], bool one_scene, int enabled, int* red) {
+  Tile<D> T;
+  T.on = false;
+  T.n = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    T.lo[a] = 0;
+    T.ext[a] = 0;
+  }
+  if (!enabled) return T;
+  const int t = threadIdx.x;
+  if (t < 2 * D) red[t] = (t < D) ? INT_MAX : INT_MIN;
+  __syncthreads();
+  int mn[D], mx[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    mn[a] = valid ? base[a] : INT_MAX;
+    mx[a] = valid ? base[a] : INT_MIN;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      float Ad = 0.0f;
-#pragma unroll
-      for (int b = 0; b < D; ++b) Ad += A[a][b] * dl[b];
-      atomic_add_f32(node + 1 + a, w * (mv[a] + Ad));
+      mn[a] = min(mn[a], __shfl_xor(mn[a], off, 64));
+      mx[a] = max(mx[a], __shfl_xor(mx[a], off, 64));
     }
-  });
+  if ((t & 63) == 0) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      atomicMin(red + a, mn[a]);
+      atomicMax(red + D + a, mx[a]);
+    }
+  }
+  __syncthreads();
+  const bool any = red[0] <= red[D];
+  int n = any ? 1 : 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    T.lo[a] = any ? red[a] : 0;
+    T.ext[a] = any ? red[D + a] - red[a] + 3 : 0;
+    n *= T.ext[a];
+  }
+  T.n = n;
+  T.on = any && one_scene && n <= kTileMax;
+  __syncthreads();
+  return T;
 }
+
+template <int D>
+__device__ __forceinline__ int tile_global_index(const Tile<D>& T, int q, int n) {
+  int l[D];
+  int r = q;
+#pragma unroll
+  for (int a = D - 1; a >= 0; --a) {
+    l[a] = r % T.ext[a];
+    r /= T.ext[a];
+  }
+  int g = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) g = g * n + T.lo[a] + l[a];
+  return g;
+}
+
+template <int D>
+__device__ __forceinline__ void tile_load(const Tile<D>& T, const float4* g, int n, float4* tile) {
+  for (int q = threadIdx.x; q < T.n; q += blockDim.x) tile[q] = g[tile_global_index<D>(T, q, n)];
+}
+
+template <int D>
+__device__ __forceinline__ void tile_zero(const Tile<D>& T, float4* tile) {
+  for (int q = threadIdx.x; q < T.n; q += blockDim.x) tile[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Adds the non-zero nodes of the tile (first NC components) into the global grid.
+template <int D, int NC>
+__device__ __forceinline__ void tile_flush(const Tile<D>& T, const float4* tile, float4* g, int n) {
+  for (int q = threadIdx.x; q < T.n; q += blockDim.x) {
+    const float4 v4 = tile[q];
+    const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+    bool nz = false;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) nz = nz || (v[c] != 0.0f);
+    if (nz) {
+      float* dst = reinterpret_cast<float*>(g + tile_global_index<D>(T, q, n));
+#pragma unroll
+      for (int c = 0; c < NC; ++c) atomic_add_f32(dst + c, v[c]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stage bodies (one particle)
+// ---------------------------------------------------------------------------
 
 // Node velocity after the grid update, from (m, P).
 template <int D>
@@ -200,67 +339,253 @@ __device__ __forceinline__ void node_velocity(const StepConsts& k, const Sten<D>
   }
 }
 
+// g2p: gather v' and C' and update the particle (v, C, x, F).
+template <int D, bool L>
+__device__ __forceinline__ void g2p_body(const StepConsts& k, const Sten<D>& st, const Nodes<D, L>& g, PState<D>& p) {
+  float vn[D] = {}, Cn[D][D] = {};
+  for_nodes<D>([&](int o0, int o1, int o2) {
+    const float w = wgt<D>(st, o0, o1, o2);
+    float dl[D], v[D];
+    delta<D>(st, o0, o1, o2, k.dx, dl);
+    node_velocity<D>(k, st, o0, o1, o2, g.get(st, o0, o1, o2), v);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      vn[c] += w * v[c];
+#pragma unroll
+      for (int b = 0; b < D; ++b) Cn[c][b] += w * v[c] * dl[b];
+    }
+  });
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+#pragma unroll
+    for (int b = 0; b < D; ++b) Cn[c][b] *= k.kappa;
+  float Fn[D][D];
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float s = p.F[c][b];
+#pragma unroll
+      for (int e = 0; e < D; ++e) s += k.dt * Cn[c][e] * p.F[e][b];
+      Fn[c][b] = s;
+    }
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    p.v[c] = vn[c];
+    p.x[c] += k.dt * vn[c];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      p.C[c][b] = Cn[c][b];
+      p.F[c][b] = Fn[c][b];
+    }
+  }
+}
+
+// p2g: scatter m and P of one particle (A and m v precomputed).
+template <int D, bool L>
+__device__ __forceinline__ void p2g_body(const StepConsts& k, const Sten<D>& st, float mass, const float (&mv)[D],
+                                         const float (&A)[D][D], const Nodes<D, L>& g) {
+  for_nodes<D>([&](int o0, int o1, int o2) {
+    const float w = wgt<D>(st, o0, o1, o2);
+    float dl[D];
+    delta<D>(st, o0, o1, o2, k.dx, dl);
+    float* node = g.at(st, o0, o1, o2);
+    atomic_add_f32(node, w * mass);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      float Ad = 0.0f;
+#pragma unroll
+      for (int b = 0; b < D; ++b) Ad += A[a][b] * dl[b];
+      atomic_add_f32(node + 1 + a, w * (mv[a] + Ad));
+    }
+  });
+}
+
+// p2g* with grid_op* folded in: accumulates into gx, gv, Abar from grid (m, P)
+// and adjoint grid (v*).
+template <int D, bool L>
+__device__ __forceinline__ void p2g_adj_body(const StepConsts& k, const Sten<D>& st, float mass, const float (&mv)[D],
+                                             const float (&A)[D][D], const Nodes<D, L>& g, const Nodes<D, L>& ad,
+                                             float (&gx)[D], float (&vb)[D], float (&Abar)[D][D]) {
+  for_nodes<D>([&](int o0, int o1, int o2) {
+    const float4 gm = g.get(st, o0, o1, o2);
+    const float4 vb4 = ad.get(st, o0, o1, o2);
+    const bool act = node_active<D>(st, o0, o1, o2, k.n, k.bound, gm.x);
+    const float inv_m = act ? 1.0f / gm.x : 0.0f;
+    const float P[3] = {gm.y, gm.z, gm.w};
+    const float V[3] = {vb4.x, vb4.y, vb4.z};
+    float Pb[D];
+    float vP = 0.0f;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      Pb[c] = V[c] * inv_m;
+      vP += V[c] * P[c];
+    }
+    const float mb = -vP * inv_m * inv_m;
+    const float w = wgt<D>(st, o0, o1, o2);
+    float dw[D], dl[D];
+    dwgt<D>(st, o0, o1, o2, k.inv_dx, dw);
+    delta<D>(st, o0, o1, o2, k.dx, dl);
+    float contrib = mass * mb;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      float Ad = 0.0f;
+#pragma unroll
+      for (int b = 0; b < D; ++b) Ad += A[c][b] * dl[b];
+      contrib += Pb[c] * (mv[c] + Ad);
+      vb[c] += w * Pb[c];
+#pragma unroll
+      for (int b = 0; b < D; ++b) Abar[c][b] += w * Pb[c] * dl[b];
+    }
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      float AtP = 0.0f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) AtP += A[c][e] * Pb[c];
+      gx[e] += contrib * dw[e] - w * AtP;
+    }
+  });
+}
+
+// C' of a particle recomputed from grid s.
+template <int D, bool L>
+__device__ __forceinline__ void g2p_C(const StepConsts& k, const Sten<D>& st, const Nodes<D, L>& g, float (&Cn)[D][D]) {
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+#pragma unroll
+    for (int b = 0; b < D; ++b) Cn[c][b] = 0.0f;
+  for_nodes<D>([&](int o0, int o1, int o2) {
+    const float w = wgt<D>(st, o0, o1, o2);
+    float dl[D], v[D];
+    delta<D>(st, o0, o1, o2, k.dx, dl);
+    node_velocity<D>(k, st, o0, o1, o2, g.get(st, o0, o1, o2), v);
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+      for (int b = 0; b < D; ++b) Cn[c][b] += w * v[c] * dl[b];
+  });
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+#pragma unroll
+    for (int b = 0; b < D; ++b) Cn[c][b] *= k.kappa;
+}
+
+// g2p*: scatter v* into the adjoint grid; accumulate x* (px).
+template <int D, bool L>
+__device__ __forceinline__ void g2p_adj_body(const StepConsts& k, const Sten<D>& st, const float (&vt)[D],
+                                             const float (&Bm)[D][D], const Nodes<D, L>& g, const Nodes<D, L>& ad,
+                                             float (&px)[D]) {
+  for_nodes<D>([&](int o0, int o1, int o2) {
+    float v[D];
+    node_velocity<D>(k, st, o0, o1, o2, g.get(st, o0, o1, o2), v);
+    const float w = wgt<D>(st, o0, o1, o2);
+    float dw[D], dl[D];
+    dwgt<D>(st, o0, o1, o2, k.inv_dx, dw);
+    delta<D>(st, o0, o1, o2, k.dx, dl);
+    float r[D], vr = 0.0f;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      float s = vt[c];
+#pragma unroll
+      for (int b = 0; b < D; ++b) s += Bm[c][b] * dl[b];
+      r[c] = s;
+      vr += v[c] * s;
+    }
+    float* node = ad.at(st, o0, o1, o2);
+#pragma unroll
+    for (int c = 0; c < D; ++c) atomic_add_f32(node + c, w * r[c]);
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      float Btv = 0.0f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) Btv += Bm[c][e] * v[c];
+      px[e] += vr * dw[e] - w * Btv;
+    }
+  });
+}
+
+template <int D>
+__device__ __forceinline__ int actuator_of(const StepConsts& k, const float* act_row, int i, float& act_tau) {
+  act_tau = 0.0f;
+  if (!act_row || !k.act_id) return -1;
+  const int aid = k.act_id[i];
+  if (aid >= 0) act_tau = k.act_strength * act_row[aid];
+  return aid;
+}
+
+// Scatter of one state into `grid` with an optional LDS tile (all threads call).
+template <int D>
+__device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i, int sc, bool one_scene,
+                                          const PState<D>& p, const float* act_row, float4* grid, float4* tile,
+                                          int* red, unsigned& err) {
+  Sten<D> st;
+  const bool fin = live && state_finite<D>(p);
+  const bool ok = fin && make_sten<D>(p.x, k.inv_dx, k.n, st);
+  if (live && !fin) err |= kErrNonfinite;
+  if (fin && !ok) err |= kErrDomain;
+  const Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
+  float4* g = grid + long(sc) * k.nodes;
+  if (T.on) {
+    tile_zero<D>(T, tile);
+    __syncthreads();
+  }
+  if (ok) {
+    const SceneParams sp = scene_params(k.E, k.nu, k.vol, k.rho, sc);
+    float act_tau;
+    actuator_of<D>(k, act_row, i, act_tau);
+    float A[D][D], FFtI[D][D], lnJ, J;
+    affine<D>(p, sp, act_tau, k.dt, k.kappa, A, FFtI, lnJ, J, err);
+    float mv[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) mv[a] = sp.mass * p.v[a];
+    if (T.on)
+      p2g_body<D, true>(k, st, sp.mass, mv, A, lds_nodes<D>(tile, T));
+    else
+      p2g_body<D, false>(k, st, sp.mass, mv, A, global_nodes<D>(g, k.n));
+  }
+  if (T.on) {
+    __syncthreads();
+    tile_flush<D, D + 1>(T, tile, g, k.n);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
 template <int D>
 __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
+  __shared__ float4 tile[kTileMax];
+  __shared__ int red[8];
   zero_range(a.clear, a.clear_n);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.k.N) return;
   const StepConsts& k = a.k;
-  const int sc = k.scene_id ? k.scene_id[i] : 0;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i < k.N;
+  const int sc = (k.scene_id && live) ? k.scene_id[i] : 0;
+  const bool one_scene = block_one_scene(k);
   unsigned err = 0;
   PState<D> p;
-  load_state<D>(a.in, i, p);
+  if (live) load_state<D>(a.in, i, p);
   if (a.do_g2p) {
     Sten<D> st;
-    const bool fin = state_finite<D>(p);
+    const bool fin = live && state_finite<D>(p);
     const bool ok = fin && make_sten<D>(p.x, k.inv_dx, k.n, st);
+    const Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
+    const float4* g = a.grid_in + long(sc) * k.nodes;
+    if (T.on) {
+      tile_load<D>(T, g, k.n, tile);
+      __syncthreads();
+    }
     if (ok) {
-      const float4* g = a.grid_in + long(sc) * k.nodes;
-      float vn[D] = {}, Cn[D][D] = {};
-      for_nodes<D>([&](int o0, int o1, int o2) {
-        const float w = wgt<D>(st, o0, o1, o2);
-        float dl[D], v[D];
-        delta<D>(st, o0, o1, o2, k.dx, dl);
-        node_velocity<D>(k, st, o0, o1, o2, g[node_of<D>(st.base, o0, o1, o2, k.n)], v);
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-          vn[c] += w * v[c];
-#pragma unroll
-          for (int b = 0; b < D; ++b) Cn[c][b] += w * v[c] * dl[b];
-        }
-      });
-      float Fn[D][D];
-#pragma unroll
-      for (int c = 0; c < D; ++c)
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-          Cn[c][b] *= k.kappa;
-        }
-#pragma unroll
-      for (int c = 0; c < D; ++c)
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-          float s = p.F[c][b];
-#pragma unroll
-          for (int e = 0; e < D; ++e) s += k.dt * Cn[c][e] * p.F[e][b];
-          Fn[c][b] = s;
-        }
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        p.v[c] = vn[c];
-        p.x[c] += k.dt * vn[c];
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-          p.C[c][b] = Cn[c][b];
-          p.F[c][b] = Fn[c][b];
-        }
-      }
-    } else {
+      if (T.on)
+        g2p_body<D, true>(k, st, lds_nodes<D>(tile, T), p);
+      else
+        g2p_body<D, false>(k, st, global_nodes<D>(g, k.n), p);
+    } else if (live) {
       err |= fin ? kErrDomain : kErrNonfinite;
     }
-    store_state<D>(a.out, i, p);
+    if (live) store_state<D>(a.out, i, p);
   }
-  if (a.do_p2g) p2g_particle<D>(k, i, sc, p, a.act_row, a.grid_out, err);
+  if (a.do_p2g) p2g_phase<D>(k, live, i, sc, one_scene, p, a.act_row, a.grid_out, tile, red, err);
   if (err) atomicOr(k.err, err);
 }
 
@@ -281,17 +606,20 @@ __device__ __forceinline__ void wave_add_keyed(bool live, int key, double val, d
 
 template <int D>
 __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
+  __shared__ float4 tileA[kTileMax];
+  __shared__ float4 tileB[kTileMax];
+  __shared__ int red[8];
   zero_range(a.clear0, a.clear0_n);
   zero_range(a.clear1, a.clear1_n);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const StepConsts& k = a.k;
   const bool live = i < k.N;
-  const int ii = live ? i : 0;
-  const int sc = (k.scene_id && live) ? k.scene_id[ii] : 0;
+  const int sc = (k.scene_id && live) ? k.scene_id[i] : 0;
+  const bool one_scene = block_one_scene(k);
   unsigned err = 0;
 
   // dL/dstate(s+1): gx, gv, gC, gF.
-  float gx[D], gv[D], gC[D][D], gF[D][D];
+  float gx[D] = {}, gv[D] = {}, gC[D][D] = {}, gF[D][D] = {};
   double eb = 0.0, actb = 0.0;
   int aid = -1;
   if (a.a_mode == 0) {
@@ -309,73 +637,44 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
           gF[c][b] = a.seed.F[(c * D + b) * a.seed.stride + i];
         }
     }
-  } else if (live) {
+  } else {
     // p2g*(s+1) with grid_op* folded into the gather.
     PState<D> p;
-    load_state<D>(a.stA, i, p);
+    if (live) {
+      load_state<D>(a.stA, i, p);
 #pragma unroll
-    for (int c = 0; c < D; ++c) gx[c] = a.partial[c * a.pstride + i];
+      for (int c = 0; c < D; ++c) gx[c] = a.partial[c * a.pstride + i];
 #pragma unroll
-    for (int c = 0; c < D; ++c)
+      for (int c = 0; c < D; ++c)
 #pragma unroll
-      for (int b = 0; b < D; ++b) gF[c][b] = a.partial[(D + c * D + b) * a.pstride + i];
-    float Abar[D][D] = {}, vb[D] = {};
+        for (int b = 0; b < D; ++b) gF[c][b] = a.partial[(D + c * D + b) * a.pstride + i];
+    }
     Sten<D> st;
-    const bool ok = state_finite<D>(p) && make_sten<D>(p.x, k.inv_dx, k.n, st);
+    const bool ok = live && state_finite<D>(p) && make_sten<D>(p.x, k.inv_dx, k.n, st);
+    const Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
+    const float4* g = a.gA + long(sc) * k.nodes;
+    const float4* ad = a.aA + long(sc) * k.nodes;
+    if (T.on) {
+      tile_load<D>(T, g, k.n, tileA);
+      tile_load<D>(T, ad, k.n, tileB);
+      __syncthreads();
+    }
     if (ok) {
       const SceneParams sp = scene_params(k.E, k.nu, k.vol, k.rho, sc);
-      float act_tau = 0.0f;
-      if (a.act_rowA && k.act_id) {
-        aid = k.act_id[i];
-        if (aid >= 0) act_tau = k.act_strength * a.act_rowA[aid];
-      }
+      float act_tau;
+      aid = actuator_of<D>(k, a.act_rowA, i, act_tau);
       float A[D][D], FFtI[D][D], lnJ, J;
       unsigned dummy = 0;
       affine<D>(p, sp, act_tau, k.dt, k.kappa, A, FFtI, lnJ, J, dummy);
       float mv[D];
 #pragma unroll
       for (int c = 0; c < D; ++c) mv[c] = sp.mass * p.v[c];
-      const float4* g = a.gA + long(sc) * k.nodes;
-      const float4* ad = a.aA + long(sc) * k.nodes;
-      for_nodes<D>([&](int o0, int o1, int o2) {
-        const int q = node_of<D>(st.base, o0, o1, o2, k.n);
-        const float4 gm = g[q];
-        const float4 vb4 = ad[q];
-        const bool act = node_active<D>(st, o0, o1, o2, k.n, k.bound, gm.x);
-        const float inv_m = act ? 1.0f / gm.x : 0.0f;
-        const float P[3] = {gm.y, gm.z, gm.w};
-        const float V[3] = {vb4.x, vb4.y, vb4.z};
-        float Pb[D];
-        float vP = 0.0f;
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-          Pb[c] = V[c] * inv_m;
-          vP += V[c] * P[c];
-        }
-        const float mb = -vP * inv_m * inv_m;
-        const float w = wgt<D>(st, o0, o1, o2);
-        float dw[D], dl[D];
-        dwgt<D>(st, o0, o1, o2, k.inv_dx, dw);
-        delta<D>(st, o0, o1, o2, k.dx, dl);
-        float contrib = sp.mass * mb;
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-          float Ad = 0.0f;
-#pragma unroll
-          for (int b = 0; b < D; ++b) Ad += A[c][b] * dl[b];
-          contrib += Pb[c] * (mv[c] + Ad);
-          vb[c] += w * Pb[c];
-#pragma unroll
-          for (int b = 0; b < D; ++b) Abar[c][b] += w * Pb[c] * dl[b];
-        }
-#pragma unroll
-        for (int e = 0; e < D; ++e) {
-          float AtP = 0.0f;
-#pragma unroll
-          for (int c = 0; c < D; ++c) AtP += A[c][e] * Pb[c];
-          gx[e] += contrib * dw[e] - w * AtP;
-        }
-      });
+      float Abar[D][D] = {}, vb[D] = {};
+      if (T.on)
+        p2g_adj_body<D, true>(k, st, sp.mass, mv, A, lds_nodes<D>(tileA, T), lds_nodes<D>(tileB, T), gx, vb, Abar);
+      else
+        p2g_adj_body<D, false>(k, st, sp.mass, mv, A, global_nodes<D>(g, k.n), global_nodes<D>(ad, k.n), gx, vb,
+                               Abar);
       const float kt = -k.dt * sp.vol * k.kappa;
       float tb[D][D], tr = 0.0f;
 #pragma unroll
@@ -406,13 +705,6 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
         }
       eb = ebf;
       actb = double(k.act_strength) * tb[1][1];
-    } else {
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        gv[c] = 0.0f;
-#pragma unroll
-        for (int b = 0; b < D; ++b) gC[c][b] = 0.0f;
-      }
     }
   }
   if (a.a_mode == 1) {
@@ -424,9 +716,9 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
       }
     }
   }
-  if (!live) return;
 
   if (a.final_out) {
+    if (!live) return;
     const int o = a.out_perm ? a.out_perm[i] : i;
     const int os = a.out.stride;
 #pragma unroll
@@ -447,42 +739,38 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   // Phase B: g2p*(s).
   {
     PState<D> p;
-    load_xF<D>(a.stB, i, p);
+    if (live) load_xF<D>(a.stB, i, p);
     float px[D], pF[D][D];
 #pragma unroll
     for (int c = 0; c < D; ++c) px[c] = gx[c];
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+      for (int b = 0; b < D; ++b) pF[c][b] = gF[c][b];
     Sten<D> st;
-    bool fin = true;
+    bool fin = live;
 #pragma unroll
     for (int c = 0; c < D; ++c) fin = fin && (p.x[c] * 0.0f == 0.0f);
     const bool ok = fin && make_sten<D>(p.x, k.inv_dx, k.n, st);
+    const Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
+    const float4* g = a.gB + long(sc) * k.nodes;
+    float4* ad = a.aB + long(sc) * k.nodes;
+    if (T.on) {
+      tile_load<D>(T, g, k.n, tileA);
+      tile_zero<D>(T, tileB);
+      __syncthreads();
+    }
     if (ok) {
-      const float4* g = a.gB + long(sc) * k.nodes;
       float Cn[D][D];
       if (a.cnext) {
 #pragma unroll
         for (int c = 0; c < D; ++c)
 #pragma unroll
           for (int b = 0; b < D; ++b) Cn[c][b] = a.cnext[(c * D + b) * a.cnext_stride + i];
+      } else if (T.on) {
+        g2p_C<D, true>(k, st, lds_nodes<D>(tileA, T), Cn);
       } else {
-#pragma unroll
-        for (int c = 0; c < D; ++c)
-#pragma unroll
-          for (int b = 0; b < D; ++b) Cn[c][b] = 0.0f;
-        for_nodes<D>([&](int o0, int o1, int o2) {
-          const float w = wgt<D>(st, o0, o1, o2);
-          float dl[D], v[D];
-          delta<D>(st, o0, o1, o2, k.dx, dl);
-          node_velocity<D>(k, st, o0, o1, o2, g[node_of<D>(st.base, o0, o1, o2, k.n)], v);
-#pragma unroll
-          for (int c = 0; c < D; ++c)
-#pragma unroll
-            for (int b = 0; b < D; ++b) Cn[c][b] += w * v[c] * dl[b];
-        });
-#pragma unroll
-        for (int c = 0; c < D; ++c)
-#pragma unroll
-          for (int b = 0; b < D; ++b) Cn[c][b] *= k.kappa;
+        g2p_C<D, false>(k, st, global_nodes<D>(g, k.n), Cn);
       }
       // F' = (I + dt C') F:  F* = (I + dt C')^T F'*,  C'* += dt F'* F^T.
       float Bm[D][D], vt[D];
@@ -502,54 +790,30 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
       // x' = x + dt v':  v'* += dt x'*.
 #pragma unroll
       for (int c = 0; c < D; ++c) vt[c] = gv[c] + k.dt * gx[c];
-      float4* ad = a.aB + long(sc) * k.nodes;
-      for_nodes<D>([&](int o0, int o1, int o2) {
-        const int q = node_of<D>(st.base, o0, o1, o2, k.n);
-        float v[D];
-        node_velocity<D>(k, st, o0, o1, o2, g[q], v);
-        const float w = wgt<D>(st, o0, o1, o2);
-        float dw[D], dl[D];
-        dwgt<D>(st, o0, o1, o2, k.inv_dx, dw);
-        delta<D>(st, o0, o1, o2, k.dx, dl);
-        float r[D], vr = 0.0f;
+      if (T.on)
+        g2p_adj_body<D, true>(k, st, vt, Bm, lds_nodes<D>(tileA, T), lds_nodes<D>(tileB, T), px);
+      else
+        g2p_adj_body<D, false>(k, st, vt, Bm, global_nodes<D>(g, k.n), global_nodes<D>(ad, k.n), px);
+    }
+    if (T.on) {
+      __syncthreads();
+      tile_flush<D, D>(T, tileB, ad, k.n);
+    }
+    if (live) {
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-          float s = vt[c];
-#pragma unroll
-          for (int b = 0; b < D; ++b) s += Bm[c][b] * dl[b];
-          r[c] = s;
-          vr += v[c] * s;
-        }
-        float* node = reinterpret_cast<float*>(ad + q);
-#pragma unroll
-        for (int c = 0; c < D; ++c) atomic_add_f32(node + c, w * r[c]);
-#pragma unroll
-        for (int e = 0; e < D; ++e) {
-          float Btv = 0.0f;
-#pragma unroll
-          for (int c = 0; c < D; ++c) Btv += Bm[c][e] * v[c];
-          px[e] += vr * dw[e] - w * Btv;
-        }
-      });
-    } else {
+      for (int c = 0; c < D; ++c) a.partial[c * a.pstride + i] = px[c];
 #pragma unroll
       for (int c = 0; c < D; ++c)
 #pragma unroll
-        for (int b = 0; b < D; ++b) pF[c][b] = gF[c][b];
+        for (int b = 0; b < D; ++b) a.partial[(D + c * D + b) * a.pstride + i] = pF[c][b];
     }
-#pragma unroll
-    for (int c = 0; c < D; ++c) a.partial[c * a.pstride + i] = px[c];
-#pragma unroll
-    for (int c = 0; c < D; ++c)
-#pragma unroll
-      for (int b = 0; b < D; ++b) a.partial[(D + c * D + b) * a.pstride + i] = pF[c][b];
   }
 
   // Phase C: recompute p2g(s-1).
   if (a.do_c) {
     PState<D> p;
-    load_state<D>(a.stC, i, p);
-    p2g_particle<D>(k, i, sc, p, a.act_rowC, a.gC, err);
+    if (live) load_state<D>(a.stC, i, p);
+    p2g_phase<D>(k, live, i, sc, one_scene, p, a.act_rowC, a.gC, tileA, red, err);
   }
   if (err) atomicOr(k.err, err);
 }

@@ -67,13 +67,16 @@ def test_checkpointed_matches_oracle():
 
 
 def test_c5_batched_subset():
-    """A few scenes of the batched workload run as one batch."""
+    """A few scenes of the batched workload run as one batch. The bodies start
+    at rest, so until they reach the floor (about step 100) they fall rigidly
+    with F = I and no stress: nothing depends on E before contact."""
     full = scenes.c5(n_scenes=6, steps=64)
     g = gpu_run(full, 64)
     o = oracle_run(full, 64)
-    # No floor contact within 64 steps: the mean-x loss does not depend on E.
     compare("c5[6]@64", full, g, o, grads=("v",), check_E=False)
+    assert np.abs(o["gE"]).max() < 1e-12 and np.abs(g["gE"]).max() < 1e-6
+    full = scenes.c5(n_scenes=6, steps=160)
     w = random_seed(full, 5)
-    g = gpu_run(full, 64, seed=w)
-    o = oracle_run(full, 64, seed=w)
-    compare("c5[6]@64 random functional", full, g, o, grads=("x", "v", "C", "F"))
+    g = gpu_run(full, 160, seed=w)
+    o = oracle_run(full, 160, seed=w)
+    compare("c5[6]@160 random functional", full, g, o, grads=("x", "v", "C", "F"))

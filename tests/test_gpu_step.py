@@ -40,10 +40,11 @@ def test_step_fwd_matches_oracle(dim, n_keep):
     ref, err = orc.step_fwd(sc, orc.pack(sc.x, sc.v, sc.C, sc.F))
     assert err == 0
     ref = orc.unpack(ref, dim)
-    x0 = sc.x.astype(np.float64)
-    r = [rel(got[0] - x0, ref[0] - x0)] + [rel(got[k], ref[k]) for k in (1, 2, 3)]
-    log(f"  rel errors (dx, v, C, F): {r}")
-    assert max(r) < 2e-5, r
+    # x' = x + dt v' is stored in FP32: x itself is compared (a one-step
+    # displacement of ~3e-4 on x ~ 0.4 has only ~1e-4 relative resolution).
+    r = [rel(got[k], ref[k]) for k in range(4)]
+    log(f"  rel errors (x, v, C, F): {r}")
+    assert r[0] < 2e-7 and max(r[1:]) < 2e-5, r
 
 
 @pytest.mark.parametrize("dim,n_keep", [(2, 1024), (2, 777), (3, 4099)])
