@@ -146,7 +146,20 @@ mpm_status mpm_bind_workspace(mpm_ctx* ctx, void* dev, size_t bytes);
 
 /* Sets a knob: "block" (threads per workgroup of the per-particle kernels:
  * 64, 128 or 256); "lds" (0/1, default 1: stage each workgroup's stencil
- * footprint in LDS when it fits, else use global memory directly); "timing" (0/1: bracket every launch of the two step
+ * footprint in LDS when it fits, else use global memory directly); "split"
+ * (0/1, default 1: run the reverse launch's grid recompute for the previous
+ * step in workgroups of its own, beside the adjoint workgroups); "remap"
+ * (0/1: interleave each workgroup's sorted particles across its waves so
+ * that fewer lanes add to one LDS node at a time); "rotate" (0/1, default
+ * 1: each lane of a wave visits its 3^d stencil nodes in an order set by its
+ * lane index, so lanes rarely add to the same node in the same instruction);
+ * "lanes" (1 or 4, default 1: lanes per particle in the step kernels; with
+ * 4, three lanes each take one slab of the 3^d stencil and the quad sums its
+ * gathers, which raises parallelism for small particle counts);
+ * "graph" (0/1, default 1:
+ * capture each tape forward/backward launch sequence once in a HIP graph on
+ * an internal stream and replay it on the caller's stream; the cache is keyed
+ * on every pointer the sequence uses); "timing" (0/1: bracket every launch of the two step
  * kernels with HIP events on the launch stream, for mpm_kernel_stats).
  * MPM_E_ARG on an unknown key or value. */
 mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value);

@@ -89,36 +89,59 @@ __device__ __forceinline__ bool state_finite(const PState<D>& p) {
 }
 
 // Per-particle stencil: base node, fractional offset f = x/dx - base in
-// [0.5, 1.5), the three B-spline pieces N_o(f) and their derivatives dN/df.
+// [0.5, 1.5), and, per axis, the three nodes base .. base+2 in the order this
+// lane visits them: the B-spline piece N (N0 = 1/2 (3/2 - f)^2,
+// N1 = 3/4 - (f - 1)^2, N2 = 1/2 (f - 1/2)^2), its derivative dN/df, the
+// offset (o - f) dx of the node from the particle, and the node coordinate.
+//
+// Visiting order: lanes of a wave that add to the same LDS or HBM node in the
+// same instruction serialise. A lane with colour (s_0, s_1, s_2) visits, at
+// step t_a of axis a, the node whose coordinate is congruent to t_a + s_a
+// (mod 3); lanes of different colours therefore never touch the same node in
+// the same instruction. Colour -1 keeps the natural order base, base+1, base+2.
 template <int D>
 struct Sten {
   int base[D] = {};
   float f[D];
   float N[D][3];
   float dN[D][3];
+  float dl[D][3];
+  int nc[D][3];
 };
 
 // Returns false when the stencil would leave [0, n) on some axis (or x is not
-// finite); base is then clamped to 0 so that no caller indexes out of bounds.
+// finite); base is then 0 so that no caller indexes out of bounds.
 template <int D>
-__device__ __forceinline__ bool make_sten(const float (&x)[D], float inv_dx, int n, Sten<D>& st) {
+__device__ __forceinline__ bool make_sten(const float (&x)[D], float inv_dx, float dx, int n, int color,
+                                          Sten<D>& st) {
   bool ok = true;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    float xs = x[a] * inv_dx;
-    float g = xs - 0.5f;
-    bool in = (g >= 0.0f) && (g < float(n - 2));
+    const float xs = x[a] * inv_dx;
+    const float g = xs - 0.5f;
+    const bool in = (g >= 0.0f) && (g < float(n - 2));
     ok = ok && in;
-    int b = in ? int(floorf(g)) : 0;
+    const int b = in ? int(floorf(g)) : 0;
     st.base[a] = b;
-    float f = xs - float(b);
+    const float f = xs - float(b);
     st.f[a] = f;
-    st.N[a][0] = 0.5f * (1.5f - f) * (1.5f - f);
-    st.N[a][1] = 0.75f - (f - 1.0f) * (f - 1.0f);
-    st.N[a][2] = 0.5f * (f - 0.5f) * (f - 0.5f);
-    st.dN[a][0] = f - 1.5f;
-    st.dN[a][1] = -2.0f * (f - 1.0f);
-    st.dN[a][2] = f - 0.5f;
+    const float w[3] = {0.5f * (1.5f - f) * (1.5f - f), 0.75f - (f - 1.0f) * (f - 1.0f), 0.5f * (f - 0.5f) * (f - 0.5f)};
+    const float dw[3] = {f - 1.5f, -2.0f * (f - 1.0f), f - 0.5f};
+    int k = 0;
+    if (color >= 0) {
+      const int digit = (D == 3) ? (a == 0 ? color / 9 : (a == 1 ? (color / 3) % 3 : color % 3))
+                                 : (a == 0 ? color / 3 : color % 3);
+      k = ((digit - b) % 3 + 3) % 3;
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      int o = t + k;
+      o = (o >= 3) ? o - 3 : o;
+      st.N[a][t] = (o == 0) ? w[0] : ((o == 1) ? w[1] : w[2]);
+      st.dN[a][t] = (o == 0) ? dw[0] : ((o == 1) ? dw[1] : dw[2]);
+      st.dl[a][t] = (float(o) - f) * dx;
+      st.nc[a][t] = b + o;
+    }
   }
   return ok;
 }
@@ -197,14 +220,6 @@ __device__ __forceinline__ void affine(const PState<D>& p, const SceneParams& sp
     }
 }
 
-template <int D>
-__device__ __forceinline__ int node_of(const int (&base)[D], int o0, int o1, int o2, int n) {
-  if constexpr (D == 2) {
-    return (base[0] + o0) * n + (base[1] + o1);
-  } else {
-    return ((base[0] + o0) * n + (base[1] + o1)) * n + (base[2] + o2);
-  }
-}
 
 __device__ __forceinline__ bool interior1(int i, int n, int bound) { return i >= bound && i < n - bound; }
 

@@ -65,8 +65,14 @@ struct mpm_ctx {
   size_t off[R_COUNT] = {}, bytes[R_COUNT] = {};
   size_t ws_bytes = 0;
   char* ws = nullptr;
-  int block = 256;
+  int block = 128;
   int lds = 1;
+  int split_c = 1;
+  int remap = 0;
+  int rotate = 1;
+  int lanes = 1;
+  int graph = 1;
+  hipStream_t capture = nullptr;
   // Per-kernel timing (knob "timing"): event pairs around each step-kernel
   // launch, read back by mpm_kernel_stats.
   bool timing = false;
@@ -95,6 +101,15 @@ struct mpm_tape {
   bool recorded = false;
   mpm_params rec{};
   std::vector<int> ring_holds;
+  // Captured launch sequences (knob "graph"): key = every pointer and size the
+  // sequence depends on plus the checkpoint-ring state it starts from; the
+  // ring state the sequence leaves behind is restored on replay.
+  struct Graph {
+    std::vector<uintptr_t> key;
+    hipGraphExec_t exec = nullptr;
+    std::vector<int> ring_after;
+  };
+  std::vector<Graph> graphs;
 
   int slot_index(int s) const {
     if (s == T) return n_ckpt;
@@ -148,6 +163,8 @@ StepConsts consts(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
   k.kappa = 4.0f / (c.dx * c.dx);
   k.act_strength = c.act_strength;
   k.lds = c.lds;
+  k.remap = c.remap;
+  k.rotate = c.rotate;
   k.scene_id = c.ns > 1 ? c.at<int>(R_SCENE_ID) : nullptr;
   k.E = p->E;
   k.nu = p->nu;
@@ -205,27 +222,30 @@ struct Timed {
   }
 };
 
-template <int D>
+template <int D, int LPP>
 mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& a, hipStream_t st) {
   Timed t(c, 0, st);
-  hipLaunchKernelGGL(mpm::k_fwd<D>, dim3(c.blocks_for(c.N)), dim3(c.block), 0, st, a);
+  hipLaunchKernelGGL((mpm::k_fwd<D, LPP>), dim3(c.blocks_for(long(c.N) * LPP)), dim3(c.block), 0, st, a);
   LAUNCH_TRY();
   return MPM_OK;
 }
 
-template <int D>
+template <int D, int LPP>
 mpm_status launch_bwd(const mpm_ctx& c, const BwdArgs& a, hipStream_t st) {
   Timed t(c, 1, st);
-  hipLaunchKernelGGL(mpm::k_bwd<D>, dim3(c.blocks_for(c.N)), dim3(c.block), 0, st, a);
+  const int nb = c.blocks_for(long(c.N) * LPP) * (a.split_c ? 2 : 1);
+  hipLaunchKernelGGL((mpm::k_bwd<D, LPP>), dim3(nb), dim3(c.block), 0, st, a);
   LAUNCH_TRY();
   return MPM_OK;
 }
 
 mpm_status fwd(const mpm_ctx& c, const FwdArgs& a, hipStream_t st) {
-  return c.d == 2 ? launch_fwd<2>(c, a, st) : launch_fwd<3>(c, a, st);
+  if (c.d == 2) return c.lanes == 4 ? launch_fwd<2, 4>(c, a, st) : launch_fwd<2, 1>(c, a, st);
+  return c.lanes == 4 ? launch_fwd<3, 4>(c, a, st) : launch_fwd<3, 1>(c, a, st);
 }
 mpm_status bwd(const mpm_ctx& c, const BwdArgs& a, hipStream_t st) {
-  return c.d == 2 ? launch_bwd<2>(c, a, st) : launch_bwd<3>(c, a, st);
+  if (c.d == 2) return c.lanes == 4 ? launch_bwd<2, 4>(c, a, st) : launch_bwd<2, 1>(c, a, st);
+  return c.lanes == 4 ? launch_bwd<3, 4>(c, a, st) : launch_bwd<3, 1>(c, a, st);
 }
 
 FwdArgs fwd_args(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
@@ -442,6 +462,7 @@ mpm_status mpm_init(const mpm_desc* desc, mpm_ctx** out) {
 void mpm_destroy(mpm_ctx* ctx) {
   if (!ctx) return;
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
   delete ctx;
 }
 
@@ -473,6 +494,31 @@ mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value) {
   if (k == "lds") {
     if (value != 0 && value != 1) return MPM_E_ARG;
     ctx->lds = int(value);
+    return MPM_OK;
+  }
+  if (k == "lanes") {
+    if (value != 1 && value != 4) return MPM_E_ARG;
+    ctx->lanes = int(value);
+    return MPM_OK;
+  }
+  if (k == "rotate") {
+    if (value != 0 && value != 1) return MPM_E_ARG;
+    ctx->rotate = int(value);
+    return MPM_OK;
+  }
+  if (k == "graph") {
+    if (value != 0 && value != 1) return MPM_E_ARG;
+    ctx->graph = int(value);
+    return MPM_OK;
+  }
+  if (k == "remap") {
+    if (value != 0 && value != 1) return MPM_E_ARG;
+    ctx->remap = int(value);
+    return MPM_OK;
+  }
+  if (k == "split") {
+    if (value != 0 && value != 1) return MPM_E_ARG;
+    ctx->split_c = int(value);
     return MPM_OK;
   }
   if (k == "timing") {
@@ -617,16 +663,19 @@ mpm_status mpm_tape_bind(mpm_tape* tape, void* dev, size_t bytes) {
   return MPM_OK;
 }
 
-void mpm_tape_destroy(mpm_tape* tape) { delete tape; }
+void mpm_tape_destroy(mpm_tape* tape) {
+  if (!tape) return;
+  for (auto& g : tape->graphs) (void)hipGraphExecDestroy(g.exec);
+  delete tape;
+}
 
-mpm_status mpm_tape_forward(mpm_tape* tape, const mpm_params* params, const mpm_state* init, mpm_state* final_state,
-                            void* stream) {
-  if (!tape || !params_ok(params) || !state_ok(init) || !state_ok(final_state)) return MPM_E_ARG;
-  if (!tape->mem) return MPM_E_TAPE;
+}  // extern "C"
+
+namespace {
+
+mpm_status enqueue_tape_forward(mpm_tape* tape, const mpm_params* params, const mpm_state* init,
+                                mpm_state* final_state, hipStream_t s) {
   mpm_ctx& c = *tape->ctx;
-  if (!c.ws) return MPM_E_STATE;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  tape->recorded = false;
   if (!tape->full) std::fill(tape->ring_holds.begin(), tape->ring_holds.end(), -1);
   const StateRef init_ref = user_ref(c, init);
   TRY(sort_particles(c, init_ref, s));
@@ -639,18 +688,12 @@ mpm_status mpm_tape_forward(mpm_tape* tape, const mpm_params* params, const mpm_
   }
   TRY(run_forward(*tape, params, 0, tape->T, s));
   TRY(scatter_state(c, tape->slot(tape->T), user_ref(c, final_state), perm, s));
-  tape->rec = *params;
-  tape->recorded = true;
   return MPM_OK;
 }
 
-mpm_status mpm_tape_backward(mpm_tape* tape, const mpm_params* params, const mpm_state* final_grad,
-                             mpm_state* init_grad, mpm_param_grad* pg, void* stream) {
-  if (!tape || !params_ok(params) || !state_ok(final_grad) || !state_ok(init_grad)) return MPM_E_ARG;
-  if (!tape->mem || !tape->recorded || !same_params(tape->rec, params)) return MPM_E_TAPE;
+mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const mpm_state* final_grad,
+                                 mpm_state* init_grad, mpm_param_grad* pg, hipStream_t s) {
   mpm_ctx& c = *tape->ctx;
-  if (!c.ws) return MPM_E_STATE;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   const int T = tape->T;
   const int* perm = c.at<int>(R_PERM);
   const int* act_id = params->act_id ? c.at<int>(R_ACT_ID) : nullptr;
@@ -699,6 +742,7 @@ mpm_status mpm_tape_backward(mpm_tape* tape, const mpm_params* params, const mpm
     b.aB = aB(st);
     if (st >= 1) {
       b.do_c = 1;
+      b.split_c = c.split_c;
       b.stC = tape->slot(st - 1);
       b.act_rowC = act_row(c, params, st - 1);
       b.gC = gB(st - 1);
@@ -734,6 +778,96 @@ mpm_status mpm_tape_backward(mpm_tape* tape, const mpm_params* params, const mpm
     LAUNCH_TRY();
   }
   return MPM_OK;
+}
+
+void push_state_key(std::vector<uintptr_t>& k, const mpm_state* st) {
+  k.push_back(reinterpret_cast<uintptr_t>(st ? st->x : nullptr));
+  k.push_back(reinterpret_cast<uintptr_t>(st ? st->v : nullptr));
+  k.push_back(reinterpret_cast<uintptr_t>(st ? st->C : nullptr));
+  k.push_back(reinterpret_cast<uintptr_t>(st ? st->F : nullptr));
+}
+
+std::vector<uintptr_t> graph_key(const mpm_tape* tape, int kind, const mpm_params* p, const mpm_state* a,
+                                 const mpm_state* b, const mpm_param_grad* pg) {
+  const mpm_ctx& c = *tape->ctx;
+  std::vector<uintptr_t> k = {uintptr_t(kind), reinterpret_cast<uintptr_t>(c.ws), reinterpret_cast<uintptr_t>(tape->mem),
+                              uintptr_t(c.block), uintptr_t(c.lds), uintptr_t(c.split_c), uintptr_t(c.remap), uintptr_t(c.rotate), uintptr_t(c.lanes),
+                              reinterpret_cast<uintptr_t>(p->E), reinterpret_cast<uintptr_t>(p->nu),
+                              reinterpret_cast<uintptr_t>(p->vol), reinterpret_cast<uintptr_t>(p->rho),
+                              reinterpret_cast<uintptr_t>(p->act_id), reinterpret_cast<uintptr_t>(p->act),
+                              reinterpret_cast<uintptr_t>(pg ? pg->E : nullptr),
+                              reinterpret_cast<uintptr_t>(pg ? pg->act : nullptr)};
+  push_state_key(k, a);
+  push_state_key(k, b);
+  for (int r : tape->ring_holds) k.push_back(uintptr_t(uint32_t(r)));
+  return k;
+}
+
+// Runs `enqueue(stream)` directly, or through a captured graph replayed on
+// `s` (captured on first use on the context's own stream).
+template <class Fn>
+mpm_status run_graphed(mpm_tape* tape, std::vector<uintptr_t> key, hipStream_t s, Fn&& enqueue) {
+  mpm_ctx& c = *tape->ctx;
+  if (!c.graph || c.timing) return enqueue(s);
+  for (auto& g : tape->graphs) {
+    if (g.key == key) {
+      HIP_TRY(hipGraphLaunch(g.exec, s));
+      tape->ring_holds = g.ring_after;
+      return MPM_OK;
+    }
+  }
+  if (!c.capture) HIP_TRY(hipStreamCreateWithFlags(&c.capture, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(c.capture, hipStreamCaptureModeThreadLocal));
+  const mpm_status st = enqueue(c.capture);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(c.capture, &graph);
+  if (st != MPM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess || !graph) return MPM_E_HIP;
+  mpm_tape::Graph g;
+  g.key = std::move(key);
+  const hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return MPM_E_HIP;
+  g.ring_after = tape->ring_holds;
+  if (tape->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(tape->graphs.front().exec);
+    tape->graphs.erase(tape->graphs.begin());
+  }
+  tape->graphs.push_back(std::move(g));
+  HIP_TRY(hipGraphLaunch(tape->graphs.back().exec, s));
+  return MPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mpm_status mpm_tape_forward(mpm_tape* tape, const mpm_params* params, const mpm_state* init, mpm_state* final_state,
+                            void* stream) {
+  if (!tape || !params_ok(params) || !state_ok(init) || !state_ok(final_state)) return MPM_E_ARG;
+  if (!tape->mem) return MPM_E_TAPE;
+  if (!tape->ctx->ws) return MPM_E_STATE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  tape->recorded = false;
+  if (!tape->full) std::fill(tape->ring_holds.begin(), tape->ring_holds.end(), -1);
+  TRY(run_graphed(tape, graph_key(tape, 0, params, init, final_state, nullptr), s,
+                  [&](hipStream_t cs) { return enqueue_tape_forward(tape, params, init, final_state, cs); }));
+  tape->rec = *params;
+  tape->recorded = true;
+  return MPM_OK;
+}
+
+mpm_status mpm_tape_backward(mpm_tape* tape, const mpm_params* params, const mpm_state* final_grad,
+                             mpm_state* init_grad, mpm_param_grad* pg, void* stream) {
+  if (!tape || !params_ok(params) || !state_ok(final_grad) || !state_ok(init_grad)) return MPM_E_ARG;
+  if (!tape->mem || !tape->recorded || !same_params(tape->rec, params)) return MPM_E_TAPE;
+  if (!tape->ctx->ws) return MPM_E_STATE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return run_graphed(tape, graph_key(tape, 1, params, final_grad, init_grad, pg), s,
+                     [&](hipStream_t cs) { return enqueue_tape_backward(tape, params, final_grad, init_grad, pg, cs); });
 }
 
 mpm_status mpm_loss(mpm_ctx* ctx, int32_t kind, int32_t axis, float sign, const mpm_state* final_state,

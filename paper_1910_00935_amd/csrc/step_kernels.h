@@ -41,6 +41,8 @@ struct StepConsts {
   int nodes;      // n^d, nodes per scene
   int n_act;      // actuator columns
   int lds;        // 1: stage gathers and scatters in LDS when the box fits
+  int remap;      // 1: interleave the workgroup's particles across waves (lane_particle)
+  int rotate;     // 1: per-lane stencil visiting order (Sten, lane_color)
   float dx, inv_dx, dt, gdt, kappa, act_strength;
   const int* scene_id;  // [N] scene of each particle, or null (one scene)
   const float* E;
@@ -90,6 +92,7 @@ struct BwdArgs {
   int pstride;
   // Phase C: p2g(s-1) recompute.
   int do_c;
+  int split_c;             // phase C in its own workgroups (grid of 2 nb)
   StateRef stC;
   const float* act_rowC;
   float4* gC;
@@ -99,16 +102,18 @@ struct BwdArgs {
   long clear1_n;
 };
 
-template <int D, class Fn>
+// Visits the stencil nodes (t0, t1, t2); S0 = 3 visits all, S0 = 1 only the
+// slab t0 = 0 (the lane's own slab when a quad of lanes shares a particle).
+template <int D, int S0, class Fn>
 __device__ __forceinline__ void for_nodes(Fn&& fn) {
   if constexpr (D == 2) {
 #pragma unroll
-    for (int o0 = 0; o0 < 3; ++o0)
+    for (int o0 = 0; o0 < S0; ++o0)
 #pragma unroll
       for (int o1 = 0; o1 < 3; ++o1) fn(o0, o1, 0);
   } else {
 #pragma unroll
-    for (int o0 = 0; o0 < 3; ++o0)
+    for (int o0 = 0; o0 < S0; ++o0)
 #pragma unroll
       for (int o1 = 0; o1 < 3; ++o1)
 #pragma unroll
@@ -138,15 +143,26 @@ __device__ __forceinline__ void dwgt(const Sten<D>& st, int o0, int o1, int o2, 
 
 template <int D>
 __device__ __forceinline__ void delta(const Sten<D>& st, int o0, int o1, int o2, float dx, float (&dl)[D]) {
-  const int o[3] = {o0, o1, o2};
-#pragma unroll
-  for (int a = 0; a < D; ++a) dl[a] = (float(o[a]) - st.f[a]) * dx;
+  (void)dx;
+  dl[0] = st.dl[0][o0];
+  dl[1] = st.dl[1][o1];
+  if constexpr (D == 3) dl[2] = st.dl[2][o2];
+}
+
+// Global index of visited node (t0, t1, t2) within its scene's grid.
+template <int D>
+__device__ __forceinline__ int node_of(const Sten<D>& st, int o0, int o1, int o2, int n) {
+  if constexpr (D == 2) {
+    return st.nc[0][o0] * n + st.nc[1][o1];
+  } else {
+    return (st.nc[0][o0] * n + st.nc[1][o1]) * n + st.nc[2][o2];
+  }
 }
 
 template <int D>
 __device__ __forceinline__ bool node_active(const Sten<D>& st, int o0, int o1, int o2, int n, int bound, float m) {
-  bool in = interior1(st.base[0] + o0, n, bound) && interior1(st.base[1] + o1, n, bound);
-  if constexpr (D == 3) in = in && interior1(st.base[2] + o2, n, bound);
+  bool in = interior1(st.nc[0][o0], n, bound) && interior1(st.nc[1][o1], n, bound);
+  if constexpr (D == 3) in = in && interior1(st.nc[2][o2], n, bound);
   return in && m > 0.0f;
 }
 
@@ -158,6 +174,56 @@ __device__ __forceinline__ void zero_range(float4* p, long n) {
 
 __device__ __forceinline__ void atomic_add_f32(float* p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add_f64(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+// Sum over the four lanes of a quad (DPP quad permutations, no LDS traffic).
+__device__ __forceinline__ float quad_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));  // [1,0,3,2]
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));  // [2,3,0,1]
+  return v;
+}
+
+template <int S0, int N>
+__device__ __forceinline__ void quad_reduce(float (&v)[N]) {
+  if constexpr (S0 == 1) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = quad_sum(v[q]);
+  }
+}
+
+template <int S0, int N, int M>
+__device__ __forceinline__ void quad_reduce(float (&v)[N][M]) {
+  if constexpr (S0 == 1) {
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+#pragma unroll
+      for (int r = 0; r < M; ++r) v[q][r] = quad_sum(v[q][r]);
+  }
+}
+
+// Quad mode: lane `sub` (0..2) of a particle's quad keeps visited node `sub`
+// of axis 0 as its slab; lane 3 keeps a zero-weight slab (it only takes part
+// in the quad reductions).
+template <int D>
+__device__ __forceinline__ void slab_select(Sten<D>& st, int sub) {
+  const bool act = sub < 3;
+  float N = st.N[0][0], dN = st.dN[0][0], dl = st.dl[0][0];
+  int nc = st.nc[0][0];
+  if (sub == 1) {
+    N = st.N[0][1];
+    dN = st.dN[0][1];
+    dl = st.dl[0][1];
+    nc = st.nc[0][1];
+  } else if (sub == 2) {
+    N = st.N[0][2];
+    dN = st.dN[0][2];
+    dl = st.dl[0][2];
+    nc = st.nc[0][2];
+  }
+  st.N[0][0] = act ? N : 0.0f;
+  st.dN[0][0] = act ? dN : 0.0f;
+  st.dl[0][0] = dl;
+  st.nc[0][0] = nc;
+}
 
 // ---------------------------------------------------------------------------
 // LDS tiles
@@ -171,33 +237,49 @@ struct Tile {
 };
 
 // Node addressing: a box of the scene's grid staged in LDS (L = true), or the
-// scene's global grid.
+// scene's global grid. LDS tiles are structure-of-arrays, component c of tile
+// node q at tile[c * kTileMax + q], so lanes touching neighbouring nodes hit
+// consecutive banks; the global grid is one float4 per node.
 template <int D, bool L>
 struct Nodes {
-  float4* p;
+  float* p;
   int lo[D], ext[D];
   int n;
   __device__ __forceinline__ int idx(const Sten<D>& st, int o0, int o1, int o2) const {
     if constexpr (L) {
       if constexpr (D == 2) {
-        return (st.base[0] + o0 - lo[0]) * ext[1] + (st.base[1] + o1 - lo[1]);
+        return (st.nc[0][o0] - lo[0]) * ext[1] + (st.nc[1][o1] - lo[1]);
       } else {
-        return ((st.base[0] + o0 - lo[0]) * ext[1] + (st.base[1] + o1 - lo[1])) * ext[2] + (st.base[2] + o2 - lo[2]);
+        return ((st.nc[0][o0] - lo[0]) * ext[1] + (st.nc[1][o1] - lo[1])) * ext[2] + (st.nc[2][o2] - lo[2]);
       }
     } else {
-      return node_of<D>(st.base, o0, o1, o2, n);
+      return node_of<D>(st, o0, o1, o2, n);
     }
   }
+  // First NC components of a node (the rest are zero).
+  template <int NC = 4>
   __device__ __forceinline__ float4 get(const Sten<D>& st, int o0, int o1, int o2) const {
-    return p[idx(st, o0, o1, o2)];
+    const int q = idx(st, o0, o1, o2);
+    if constexpr (L) {
+      float4 v = make_float4(p[q], 0.f, 0.f, 0.f);
+      if (NC > 1) v.y = p[kTileMax + q];
+      if (NC > 2) v.z = p[2 * kTileMax + q];
+      if (NC > 3) v.w = p[3 * kTileMax + q];
+      return v;
+    } else {
+      return reinterpret_cast<const float4*>(p)[q];
+    }
   }
-  __device__ __forceinline__ float* at(const Sten<D>& st, int o0, int o1, int o2) const {
-    return reinterpret_cast<float*>(p + idx(st, o0, o1, o2));
+  __device__ __forceinline__ void add(int q, int c, float v) const {
+    if constexpr (L)
+      atomic_add_f32(p + c * kTileMax + q, v);
+    else
+      atomic_add_f32(p + 4 * q + c, v);
   }
 };
 
 template <int D>
-__device__ __forceinline__ Nodes<D, true> lds_nodes(float4* tile, const Tile<D>& T) {
+__device__ __forceinline__ Nodes<D, true> lds_nodes(float* tile, const Tile<D>& T) {
   Nodes<D, true> a;
   a.p = tile;
 #pragma unroll
@@ -212,7 +294,7 @@ __device__ __forceinline__ Nodes<D, true> lds_nodes(float4* tile, const Tile<D>&
 template <int D>
 __device__ __forceinline__ Nodes<D, false> global_nodes(const float4* g, int n) {
   Nodes<D, false> a;
-  a.p = const_cast<float4*>(g);
+  a.p = reinterpret_cast<float*>(const_cast<float4*>(g));
 #pragma unroll
   for (int q = 0; q < D; ++q) {
     a.lo[q] = 0;
@@ -222,11 +304,37 @@ __device__ __forceinline__ Nodes<D, false> global_nodes(const float4* g, int n) 
   return a;
 }
 
-// True when every particle of this workgroup belongs to one scene.
-__device__ __forceinline__ bool block_one_scene(const StepConsts& k) {
+// Stencil visiting colour of this lane (see Sten): lane mod 3^d, or -1.
+template <int D, int LPP>
+__device__ __forceinline__ int lane_color(const StepConsts& k) {
+  return k.rotate ? (int(threadIdx.x & 63) / LPP) % (D == 3 ? 27 : 9) : -1;
+}
+
+// Stencil of the particle at x for this lane (quad mode: the lane's slab).
+template <int D, int LPP>
+__device__ __forceinline__ bool lane_sten(const StepConsts& k, const float (&x)[D], int sub, Sten<D>& st) {
+  const bool ok = make_sten<D>(x, k.inv_dx, k.dx, k.n, lane_color<D, LPP>(k), st);
+  if constexpr (LPP == 4) slab_select<D>(st, sub);
+  return ok;
+}
+
+// Particle (within its workgroup) handled by thread t. Particles are sorted by
+// stencil base, so runs of consecutive particles share all their stencil
+// nodes, and lanes of one wave adding to the same LDS node in the same
+// instruction serialise. With remap, the B particles of the workgroup are read
+// as a (B/8) x 8 matrix of consecutive groups of 8 and thread t takes row
+// t % (B/8), column t / (B/8): a wave then holds at most 64 / (B/8) particles
+// of any group of 8.
+__device__ __forceinline__ int lane_particle(int t, int B, int remap) {
+  if (!remap || (B & 7)) return t;
+  const int rows = B >> 3;
+  return (t % rows) * 8 + t / rows;
+}
+
+// True when the `count` particles of the workgroup starting at `first` belong to one scene.
+__device__ __forceinline__ bool block_one_scene(const StepConsts& k, int first, int count) {
   if (!k.scene_id) return true;
-  const int first = blockIdx.x * blockDim.x;
-  const int last = min(first + int(blockDim.x), k.N) - 1;
+  const int last = min(first + count, k.N) - 1;
   return k.scene_id[first] == k.scene_id[last];
 }
 
@@ -295,25 +403,36 @@ __device__ __forceinline__ int tile_global_index(const Tile<D>& T, int q, int n)
   return g;
 }
 
-template <int D>
-__device__ __forceinline__ void tile_load(const Tile<D>& T, const float4* g, int n, float4* tile) {
-  for (int q = threadIdx.x; q < T.n; q += blockDim.x) tile[q] = g[tile_global_index<D>(T, q, n)];
+// Loads the first NC components of the box's nodes into a SoA tile.
+template <int D, int NC>
+__device__ __forceinline__ void tile_load(const Tile<D>& T, const float4* g, int n, float* tile) {
+  for (int q = threadIdx.x; q < T.n; q += blockDim.x) {
+    const float4 v = g[tile_global_index<D>(T, q, n)];
+    tile[q] = v.x;
+    if (NC > 1) tile[kTileMax + q] = v.y;
+    if (NC > 2) tile[2 * kTileMax + q] = v.z;
+    if (NC > 3) tile[3 * kTileMax + q] = v.w;
+  }
 }
 
-template <int D>
-__device__ __forceinline__ void tile_zero(const Tile<D>& T, float4* tile) {
-  for (int q = threadIdx.x; q < T.n; q += blockDim.x) tile[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+template <int D, int NC>
+__device__ __forceinline__ void tile_zero(const Tile<D>& T, float* tile) {
+  for (int q = threadIdx.x; q < T.n; q += blockDim.x)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) tile[c * kTileMax + q] = 0.0f;
 }
 
 // Adds the non-zero nodes of the tile (first NC components) into the global grid.
 template <int D, int NC>
-__device__ __forceinline__ void tile_flush(const Tile<D>& T, const float4* tile, float4* g, int n) {
+__device__ __forceinline__ void tile_flush(const Tile<D>& T, const float* tile, float4* g, int n) {
   for (int q = threadIdx.x; q < T.n; q += blockDim.x) {
-    const float4 v4 = tile[q];
-    const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+    float v[NC];
     bool nz = false;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) nz = nz || (v[c] != 0.0f);
+    for (int c = 0; c < NC; ++c) {
+      v[c] = tile[c * kTileMax + q];
+      nz = nz || (v[c] != 0.0f);
+    }
     if (nz) {
       float* dst = reinterpret_cast<float*>(g + tile_global_index<D>(T, q, n));
 #pragma unroll
@@ -340,14 +459,14 @@ __device__ __forceinline__ void node_velocity(const StepConsts& k, const Sten<D>
 }
 
 // g2p: gather v' and C' and update the particle (v, C, x, F).
-template <int D, bool L>
+template <int D, bool L, int S0>
 __device__ __forceinline__ void g2p_body(const StepConsts& k, const Sten<D>& st, const Nodes<D, L>& g, PState<D>& p) {
   float vn[D] = {}, Cn[D][D] = {};
-  for_nodes<D>([&](int o0, int o1, int o2) {
+  for_nodes<D, S0>([&](int o0, int o1, int o2) {
     const float w = wgt<D>(st, o0, o1, o2);
     float dl[D], v[D];
     delta<D>(st, o0, o1, o2, k.dx, dl);
-    node_velocity<D>(k, st, o0, o1, o2, g.get(st, o0, o1, o2), v);
+    node_velocity<D>(k, st, o0, o1, o2, g.template get<D + 1>(st, o0, o1, o2), v);
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       vn[c] += w * v[c];
@@ -355,6 +474,8 @@ __device__ __forceinline__ void g2p_body(const StepConsts& k, const Sten<D>& st,
       for (int b = 0; b < D; ++b) Cn[c][b] += w * v[c] * dl[b];
     }
   });
+  quad_reduce<S0>(vn);
+  quad_reduce<S0>(Cn);
 #pragma unroll
   for (int c = 0; c < D; ++c)
 #pragma unroll
@@ -382,34 +503,35 @@ __device__ __forceinline__ void g2p_body(const StepConsts& k, const Sten<D>& st,
 }
 
 // p2g: scatter m and P of one particle (A and m v precomputed).
-template <int D, bool L>
+template <int D, bool L, int S0>
 __device__ __forceinline__ void p2g_body(const StepConsts& k, const Sten<D>& st, float mass, const float (&mv)[D],
                                          const float (&A)[D][D], const Nodes<D, L>& g) {
-  for_nodes<D>([&](int o0, int o1, int o2) {
+  for_nodes<D, S0>([&](int o0, int o1, int o2) {
     const float w = wgt<D>(st, o0, o1, o2);
     float dl[D];
     delta<D>(st, o0, o1, o2, k.dx, dl);
-    float* node = g.at(st, o0, o1, o2);
-    atomic_add_f32(node, w * mass);
+    const int q = g.idx(st, o0, o1, o2);
+    g.add(q, 0, w * mass);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       float Ad = 0.0f;
 #pragma unroll
       for (int b = 0; b < D; ++b) Ad += A[a][b] * dl[b];
-      atomic_add_f32(node + 1 + a, w * (mv[a] + Ad));
+      g.add(q, 1 + a, w * (mv[a] + Ad));
     }
   });
 }
 
 // p2g* with grid_op* folded in: accumulates into gx, gv, Abar from grid (m, P)
 // and adjoint grid (v*).
-template <int D, bool L>
+template <int D, bool L, int S0>
 __device__ __forceinline__ void p2g_adj_body(const StepConsts& k, const Sten<D>& st, float mass, const float (&mv)[D],
                                              const float (&A)[D][D], const Nodes<D, L>& g, const Nodes<D, L>& ad,
                                              float (&gx)[D], float (&vb)[D], float (&Abar)[D][D]) {
-  for_nodes<D>([&](int o0, int o1, int o2) {
-    const float4 gm = g.get(st, o0, o1, o2);
-    const float4 vb4 = ad.get(st, o0, o1, o2);
+  float gxa[D] = {};
+  for_nodes<D, S0>([&](int o0, int o1, int o2) {
+    const float4 gm = g.template get<D + 1>(st, o0, o1, o2);
+    const float4 vb4 = ad.template get<D>(st, o0, o1, o2);
     const bool act = node_active<D>(st, o0, o1, o2, k.n, k.bound, gm.x);
     const float inv_m = act ? 1.0f / gm.x : 0.0f;
     const float P[3] = {gm.y, gm.z, gm.w};
@@ -442,28 +564,34 @@ __device__ __forceinline__ void p2g_adj_body(const StepConsts& k, const Sten<D>&
       float AtP = 0.0f;
 #pragma unroll
       for (int c = 0; c < D; ++c) AtP += A[c][e] * Pb[c];
-      gx[e] += contrib * dw[e] - w * AtP;
+      gxa[e] += contrib * dw[e] - w * AtP;
     }
   });
+  quad_reduce<S0>(gxa);
+  quad_reduce<S0>(vb);
+  quad_reduce<S0>(Abar);
+#pragma unroll
+  for (int e = 0; e < D; ++e) gx[e] += gxa[e];
 }
 
 // C' of a particle recomputed from grid s.
-template <int D, bool L>
+template <int D, bool L, int S0>
 __device__ __forceinline__ void g2p_C(const StepConsts& k, const Sten<D>& st, const Nodes<D, L>& g, float (&Cn)[D][D]) {
 #pragma unroll
   for (int c = 0; c < D; ++c)
 #pragma unroll
     for (int b = 0; b < D; ++b) Cn[c][b] = 0.0f;
-  for_nodes<D>([&](int o0, int o1, int o2) {
+  for_nodes<D, S0>([&](int o0, int o1, int o2) {
     const float w = wgt<D>(st, o0, o1, o2);
     float dl[D], v[D];
     delta<D>(st, o0, o1, o2, k.dx, dl);
-    node_velocity<D>(k, st, o0, o1, o2, g.get(st, o0, o1, o2), v);
+    node_velocity<D>(k, st, o0, o1, o2, g.template get<D + 1>(st, o0, o1, o2), v);
 #pragma unroll
     for (int c = 0; c < D; ++c)
 #pragma unroll
       for (int b = 0; b < D; ++b) Cn[c][b] += w * v[c] * dl[b];
   });
+  quad_reduce<S0>(Cn);
 #pragma unroll
   for (int c = 0; c < D; ++c)
 #pragma unroll
@@ -471,13 +599,14 @@ __device__ __forceinline__ void g2p_C(const StepConsts& k, const Sten<D>& st, co
 }
 
 // g2p*: scatter v* into the adjoint grid; accumulate x* (px).
-template <int D, bool L>
+template <int D, bool L, int S0>
 __device__ __forceinline__ void g2p_adj_body(const StepConsts& k, const Sten<D>& st, const float (&vt)[D],
                                              const float (&Bm)[D][D], const Nodes<D, L>& g, const Nodes<D, L>& ad,
-                                             float (&px)[D]) {
-  for_nodes<D>([&](int o0, int o1, int o2) {
+                                             float (&px)[D], bool scatter) {
+  float pxa[D] = {};
+  for_nodes<D, S0>([&](int o0, int o1, int o2) {
     float v[D];
-    node_velocity<D>(k, st, o0, o1, o2, g.get(st, o0, o1, o2), v);
+    node_velocity<D>(k, st, o0, o1, o2, g.template get<D + 1>(st, o0, o1, o2), v);
     const float w = wgt<D>(st, o0, o1, o2);
     float dw[D], dl[D];
     dwgt<D>(st, o0, o1, o2, k.inv_dx, dw);
@@ -491,17 +620,22 @@ __device__ __forceinline__ void g2p_adj_body(const StepConsts& k, const Sten<D>&
       r[c] = s;
       vr += v[c] * s;
     }
-    float* node = ad.at(st, o0, o1, o2);
+    if (scatter) {
+      const int q = ad.idx(st, o0, o1, o2);
 #pragma unroll
-    for (int c = 0; c < D; ++c) atomic_add_f32(node + c, w * r[c]);
+      for (int c = 0; c < D; ++c) ad.add(q, c, w * r[c]);
+    }
 #pragma unroll
     for (int e = 0; e < D; ++e) {
       float Btv = 0.0f;
 #pragma unroll
       for (int c = 0; c < D; ++c) Btv += Bm[c][e] * v[c];
-      px[e] += vr * dw[e] - w * Btv;
+      pxa[e] += vr * dw[e] - w * Btv;
     }
   });
+  quad_reduce<S0>(pxa);
+#pragma unroll
+  for (int e = 0; e < D; ++e) px[e] += pxa[e];
 }
 
 template <int D>
@@ -514,19 +648,20 @@ __device__ __forceinline__ int actuator_of(const StepConsts& k, const float* act
 }
 
 // Scatter of one state into `grid` with an optional LDS tile (all threads call).
-template <int D>
-__device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i, int sc, bool one_scene,
-                                          const PState<D>& p, const float* act_row, float4* grid, float4* tile,
+template <int D, int LPP>
+__device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i, int sc, bool one_scene, int sub,
+                                          const PState<D>& p, const float* act_row, float4* grid, float* tile,
                                           int* red, unsigned& err) {
+  constexpr int S0 = (LPP == 4) ? 1 : 3;
   Sten<D> st;
   const bool fin = live && state_finite<D>(p);
-  const bool ok = fin && make_sten<D>(p.x, k.inv_dx, k.n, st);
+  const bool ok = fin && lane_sten<D, LPP>(k, p.x, sub, st);
   if (live && !fin) err |= kErrNonfinite;
   if (fin && !ok) err |= kErrDomain;
   const Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
   float4* g = grid + long(sc) * k.nodes;
   if (T.on) {
-    tile_zero<D>(T, tile);
+    tile_zero<D, D + 1>(T, tile);
     __syncthreads();
   }
   if (ok) {
@@ -538,10 +673,12 @@ __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i,
     float mv[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) mv[a] = sp.mass * p.v[a];
-    if (T.on)
-      p2g_body<D, true>(k, st, sp.mass, mv, A, lds_nodes<D>(tile, T));
-    else
-      p2g_body<D, false>(k, st, sp.mass, mv, A, global_nodes<D>(g, k.n));
+    if (LPP == 1 || sub < 3) {
+      if (T.on)
+        p2g_body<D, true, S0>(k, st, sp.mass, mv, A, lds_nodes<D>(tile, T));
+      else
+        p2g_body<D, false, S0>(k, st, sp.mass, mv, A, global_nodes<D>(g, k.n));
+    }
   }
   if (T.on) {
     __syncthreads();
@@ -552,40 +689,67 @@ __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i,
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-template <int D>
+// Thread -> particle mapping. LPP = 1: one lane per particle (optionally
+// interleaved, lane_particle). LPP = 4: a quad of lanes per particle; lanes
+// 0..2 each take one slab of the stencil (t0 = 0, 1, 2), lane 3 only joins
+// the quad reductions; lane 0 of the quad writes the particle's outputs.
+template <int LPP>
+struct LaneMap {
+  int first, i, sub, count;
+  bool live, owner;
+  __device__ __forceinline__ LaneMap(const StepConsts& k, int block_index) {
+    count = int(blockDim.x) / LPP;
+    first = block_index * count;
+    if constexpr (LPP == 4) {
+      sub = int(threadIdx.x & 3);
+      i = first + int(threadIdx.x >> 2);
+    } else {
+      sub = 0;
+      i = first + lane_particle(threadIdx.x, blockDim.x, k.remap);
+    }
+    live = i < k.N;
+    owner = sub == 0;
+  }
+};
+
+template <int D, int LPP>
 __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
-  __shared__ float4 tile[kTileMax];
+  constexpr int S0 = (LPP == 4) ? 1 : 3;
+  __shared__ float tile[4 * kTileMax];
   __shared__ int red[8];
   zero_range(a.clear, a.clear_n);
   const StepConsts& k = a.k;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = i < k.N;
-  const int sc = (k.scene_id && live) ? k.scene_id[i] : 0;
-  const bool one_scene = block_one_scene(k);
+  const LaneMap<LPP> lm(k, int(blockIdx.x));
+  const int first = lm.first, i = lm.i, sub = lm.sub;
+  const bool live = lm.live;
+  // Threads past the end take the scene of the workgroup's first particle:
+  // they still load and flush the workgroup's LDS tile.
+  const int sc = k.scene_id ? k.scene_id[live ? i : first] : 0;
+  const bool one_scene = block_one_scene(k, first, lm.count);
   unsigned err = 0;
   PState<D> p;
   if (live) load_state<D>(a.in, i, p);
   if (a.do_g2p) {
     Sten<D> st;
     const bool fin = live && state_finite<D>(p);
-    const bool ok = fin && make_sten<D>(p.x, k.inv_dx, k.n, st);
+    const bool ok = fin && lane_sten<D, LPP>(k, p.x, sub, st);
     const Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
     const float4* g = a.grid_in + long(sc) * k.nodes;
     if (T.on) {
-      tile_load<D>(T, g, k.n, tile);
+      tile_load<D, D + 1>(T, g, k.n, tile);
       __syncthreads();
     }
     if (ok) {
       if (T.on)
-        g2p_body<D, true>(k, st, lds_nodes<D>(tile, T), p);
+        g2p_body<D, true, S0>(k, st, lds_nodes<D>(tile, T), p);
       else
-        g2p_body<D, false>(k, st, global_nodes<D>(g, k.n), p);
+        g2p_body<D, false, S0>(k, st, global_nodes<D>(g, k.n), p);
     } else if (live) {
       err |= fin ? kErrDomain : kErrNonfinite;
     }
-    if (live) store_state<D>(a.out, i, p);
+    if (live && lm.owner) store_state<D>(a.out, i, p);
   }
-  if (a.do_p2g) p2g_phase<D>(k, live, i, sc, one_scene, p, a.act_row, a.grid_out, tile, red, err);
+  if (a.do_p2g) p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_row, a.grid_out, tile, red, err);
   if (err) atomicOr(k.err, err);
 }
 
@@ -604,19 +768,35 @@ __device__ __forceinline__ void wave_add_keyed(bool live, int key, double val, d
   }
 }
 
-template <int D>
+template <int D, int LPP>
 __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
-  __shared__ float4 tileA[kTileMax];
-  __shared__ float4 tileB[kTileMax];
+  constexpr int S0 = (LPP == 4) ? 1 : 3;
+  __shared__ float tileA[4 * kTileMax];
+  __shared__ float tileB[4 * kTileMax];
   __shared__ int red[8];
   zero_range(a.clear0, a.clear0_n);
   zero_range(a.clear1, a.clear1_n);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const StepConsts& k = a.k;
-  const bool live = i < k.N;
-  const int sc = (k.scene_id && live) ? k.scene_id[i] : 0;
-  const bool one_scene = block_one_scene(k);
+  // With split_c, workgroups [0, nb) run phases A and B and workgroups
+  // [nb, 2 nb) run phase C on the same particles: C does not depend on A or B.
+  const int per_block = int(blockDim.x) / LPP;
+  const int nb = (k.N + per_block - 1) / per_block;
+  const bool role_c = a.split_c && int(blockIdx.x) >= nb;
+  const LaneMap<LPP> lm(k, role_c ? int(blockIdx.x) - nb : int(blockIdx.x));
+  const int first = lm.first, i = lm.i, sub = lm.sub;
+  const bool live = lm.live, owner = lm.owner;
+  // Threads past the end take the scene of the workgroup's first particle:
+  // they still load and flush the workgroup's LDS tile.
+  const int sc = k.scene_id ? k.scene_id[live ? i : first] : 0;
+  const bool one_scene = block_one_scene(k, first, lm.count);
   unsigned err = 0;
+  if (role_c) {
+    PState<D> p;
+    if (live) load_state<D>(a.stC, i, p);
+    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tileA, red, err);
+    if (err) atomicOr(k.err, err);
+    return;
+  }
 
   // dL/dstate(s+1): gx, gv, gC, gF.
   float gx[D] = {}, gv[D] = {}, gC[D][D] = {}, gF[D][D] = {};
@@ -650,13 +830,13 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
         for (int b = 0; b < D; ++b) gF[c][b] = a.partial[(D + c * D + b) * a.pstride + i];
     }
     Sten<D> st;
-    const bool ok = live && state_finite<D>(p) && make_sten<D>(p.x, k.inv_dx, k.n, st);
+    const bool ok = live && state_finite<D>(p) && lane_sten<D, LPP>(k, p.x, sub, st);
     const Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
     const float4* g = a.gA + long(sc) * k.nodes;
     const float4* ad = a.aA + long(sc) * k.nodes;
     if (T.on) {
-      tile_load<D>(T, g, k.n, tileA);
-      tile_load<D>(T, ad, k.n, tileB);
+      tile_load<D, D + 1>(T, g, k.n, tileA);
+      tile_load<D, D>(T, ad, k.n, tileB);
       __syncthreads();
     }
     if (ok) {
@@ -671,10 +851,11 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
       for (int c = 0; c < D; ++c) mv[c] = sp.mass * p.v[c];
       float Abar[D][D] = {}, vb[D] = {};
       if (T.on)
-        p2g_adj_body<D, true>(k, st, sp.mass, mv, A, lds_nodes<D>(tileA, T), lds_nodes<D>(tileB, T), gx, vb, Abar);
+        p2g_adj_body<D, true, S0>(k, st, sp.mass, mv, A, lds_nodes<D>(tileA, T), lds_nodes<D>(tileB, T), gx, vb,
+                                  Abar);
       else
-        p2g_adj_body<D, false>(k, st, sp.mass, mv, A, global_nodes<D>(g, k.n), global_nodes<D>(ad, k.n), gx, vb,
-                               Abar);
+        p2g_adj_body<D, false, S0>(k, st, sp.mass, mv, A, global_nodes<D>(g, k.n), global_nodes<D>(ad, k.n), gx, vb,
+                                   Abar);
       const float kt = -k.dt * sp.vol * k.kappa;
       float tb[D][D], tr = 0.0f;
 #pragma unroll
@@ -708,17 +889,17 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     }
   }
   if (a.a_mode == 1) {
-    if (a.gE) wave_add_keyed(live, sc, eb, a.gE);
+    if (a.gE) wave_add_keyed(live && owner, sc, eb, a.gE);
     if (a.gact_rowA && k.act_id) {
       for (int kk = 0; kk < k.n_act; ++kk) {
-        const double s = wave_sum((live && aid == kk) ? actb : 0.0);
+        const double s = wave_sum((live && owner && aid == kk) ? actb : 0.0);
         if ((threadIdx.x & 63) == 0 && s != 0.0) atomic_add_f64(a.gact_rowA + kk, s);
       }
     }
   }
 
   if (a.final_out) {
-    if (!live) return;
+    if (!live || !owner) return;
     const int o = a.out_perm ? a.out_perm[i] : i;
     const int os = a.out.stride;
 #pragma unroll
@@ -751,13 +932,13 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     bool fin = live;
 #pragma unroll
     for (int c = 0; c < D; ++c) fin = fin && (p.x[c] * 0.0f == 0.0f);
-    const bool ok = fin && make_sten<D>(p.x, k.inv_dx, k.n, st);
+    const bool ok = fin && lane_sten<D, LPP>(k, p.x, sub, st);
     const Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
     const float4* g = a.gB + long(sc) * k.nodes;
     float4* ad = a.aB + long(sc) * k.nodes;
     if (T.on) {
-      tile_load<D>(T, g, k.n, tileA);
-      tile_zero<D>(T, tileB);
+      tile_load<D, D + 1>(T, g, k.n, tileA);
+      tile_zero<D, D>(T, tileB);
       __syncthreads();
     }
     if (ok) {
@@ -768,9 +949,9 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
 #pragma unroll
           for (int b = 0; b < D; ++b) Cn[c][b] = a.cnext[(c * D + b) * a.cnext_stride + i];
       } else if (T.on) {
-        g2p_C<D, true>(k, st, lds_nodes<D>(tileA, T), Cn);
+        g2p_C<D, true, S0>(k, st, lds_nodes<D>(tileA, T), Cn);
       } else {
-        g2p_C<D, false>(k, st, global_nodes<D>(g, k.n), Cn);
+        g2p_C<D, false, S0>(k, st, global_nodes<D>(g, k.n), Cn);
       }
       // F' = (I + dt C') F:  F* = (I + dt C')^T F'*,  C'* += dt F'* F^T.
       float Bm[D][D], vt[D];
@@ -790,16 +971,17 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
       // x' = x + dt v':  v'* += dt x'*.
 #pragma unroll
       for (int c = 0; c < D; ++c) vt[c] = gv[c] + k.dt * gx[c];
+      const bool scatter = LPP == 1 || sub < 3;
       if (T.on)
-        g2p_adj_body<D, true>(k, st, vt, Bm, lds_nodes<D>(tileA, T), lds_nodes<D>(tileB, T), px);
+        g2p_adj_body<D, true, S0>(k, st, vt, Bm, lds_nodes<D>(tileA, T), lds_nodes<D>(tileB, T), px, scatter);
       else
-        g2p_adj_body<D, false>(k, st, vt, Bm, global_nodes<D>(g, k.n), global_nodes<D>(ad, k.n), px);
+        g2p_adj_body<D, false, S0>(k, st, vt, Bm, global_nodes<D>(g, k.n), global_nodes<D>(ad, k.n), px, scatter);
     }
     if (T.on) {
       __syncthreads();
       tile_flush<D, D>(T, tileB, ad, k.n);
     }
-    if (live) {
+    if (live && owner) {
 #pragma unroll
       for (int c = 0; c < D; ++c) a.partial[c * a.pstride + i] = px[c];
 #pragma unroll
@@ -810,10 +992,10 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   }
 
   // Phase C: recompute p2g(s-1).
-  if (a.do_c) {
+  if (a.do_c && !a.split_c) {
     PState<D> p;
     if (live) load_state<D>(a.stC, i, p);
-    p2g_phase<D>(k, live, i, sc, one_scene, p, a.act_rowC, a.gC, tileA, red, err);
+    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tileA, red, err);
   }
   if (err) atomicOr(k.err, err);
 }

@@ -119,7 +119,7 @@ class Simulator:
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx is not None and ctx.value:
+        if ctx is not None and ctx.value and L is not None and L._lib is not None:
             L.mpm_destroy(ctx)
             self.ctx = None
 
@@ -173,7 +173,7 @@ class Tape:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and L is not None and L._lib is not None:
             L.mpm_tape_destroy(h)
             self.h = None
 

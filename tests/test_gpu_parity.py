@@ -34,27 +34,35 @@ def test_c1_closed_form_and_oracle():
     compare("c1", sc, g, o, grads=("v",), check_E=False)
 
 
-def test_c1d_parity():
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_c1d_parity(lanes):
     """Deforming 2D body: mean-x loss gradients, then a random functional of the
     final state for every input block and E."""
     sc = scenes.c1d()
-    g = gpu_run(sc, sc.steps)
+    g = gpu_run(sc, sc.steps, knobs={"lanes": lanes})
     o = oracle_run(sc, sc.steps)
     compare("c1d", sc, g, o, grads=("x", "v"), check_E=False)
     assert abs(o["gE"][0]) < 1e-15 and abs(g["gE"][0]) < 1e-6  # momentum conservation: dL/dE = 0
     w = random_seed(sc)
-    g = gpu_run(sc, sc.steps, seed=w)
+    g = gpu_run(sc, sc.steps, seed=w, knobs={"lanes": lanes})
     o = oracle_run(sc, sc.steps, seed=w)
-    compare("c1d random functional", sc, g, o, grads=("x", "v", "C", "F"))
+    compare(f"c1d random functional lanes={lanes}", sc, g, o, grads=("x", "v", "C", "F"))
 
 
-@pytest.mark.parametrize("block", [64, 256])
-def test_c3_parity_64_steps(block):
-    """3D workload c3 (64^3 grid, 32768 particles) gated at 64 steps."""
+@pytest.fixture(scope="module")
+def c3_oracle_64():
     sc = scenes.c3().with_steps(64)
-    g = gpu_run(sc, 64, knobs={"block": block})
-    o = oracle_run(sc, 64)
-    compare(f"c3@64 block={block}", sc, g, o, grads=("v", "x"), check_E=False)
+    return sc, oracle_run(sc, 64)
+
+
+@pytest.mark.parametrize("knobs", [dict(block=64), dict(block=128), dict(block=256), dict(block=128, lanes=4),
+                                   dict(block=256, lanes=4, rotate=0), dict(block=128, lds=0, remap=1)])
+def test_c3_parity_64_steps(knobs, c3_oracle_64):
+    """3D workload c3 (64^3 grid, 32768 particles) gated at 64 steps, in each
+    launch configuration."""
+    sc, o = c3_oracle_64
+    g = gpu_run(sc, 64, knobs=knobs)
+    compare(f"c3@64 {knobs}", sc, g, o, grads=("v", "x"), check_E=False)
 
 
 def test_checkpointed_matches_oracle():
@@ -66,17 +74,18 @@ def test_checkpointed_matches_oracle():
     compare("c1d@20 K=4", sc, g, o, grads=("x", "v", "C", "F"))
 
 
-def test_c5_batched_subset():
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_c5_batched_subset(lanes):
     """A few scenes of the batched workload run as one batch. The bodies start
     at rest, so until they reach the floor (about step 100) they fall rigidly
     with F = I and no stress: nothing depends on E before contact."""
     full = scenes.c5(n_scenes=6, steps=64)
-    g = gpu_run(full, 64)
+    g = gpu_run(full, 64, knobs={"lanes": lanes})
     o = oracle_run(full, 64)
     compare("c5[6]@64", full, g, o, grads=("v",), check_E=False)
     assert np.abs(o["gE"]).max() < 1e-12 and np.abs(g["gE"]).max() < 1e-6
     full = scenes.c5(n_scenes=6, steps=160)
     w = random_seed(full, 5)
-    g = gpu_run(full, 160, seed=w)
+    g = gpu_run(full, 160, seed=w, knobs={"lanes": lanes})
     o = oracle_run(full, 160, seed=w)
     compare("c5[6]@160 random functional", full, g, o, grads=("x", "v", "C", "F"))

@@ -26,11 +26,12 @@ def _case(dim, n_keep):
     return scenes.random_state(base, seed=10 + dim)
 
 
+@pytest.mark.parametrize("lanes", [1, 4])
 @pytest.mark.parametrize("dim,n_keep", [(2, 1024), (2, 777), (3, 4099)])
-def test_step_fwd_matches_oracle(dim, n_keep):
+def test_step_fwd_matches_oracle(dim, n_keep, lanes):
     sc = _case(dim, n_keep)
-    log(f"[step_fwd] dim={dim} N={sc.n_particles}")
-    sim = rt.Simulator.for_scene(sc)
+    log(f"[step_fwd] dim={dim} N={sc.n_particles} lanes={lanes}")
+    sim = rt.Simulator.for_scene(sc, knobs={"lanes": lanes})
     p = rt.params_for_scene(sc)
     s_in = rt.state_for_scene(sc)
     s_out = rt.State.empty(dim, sc.n_particles)
@@ -47,14 +48,15 @@ def test_step_fwd_matches_oracle(dim, n_keep):
     assert r[0] < 2e-7 and max(r[1:]) < 2e-5, r
 
 
+@pytest.mark.parametrize("lanes", [1, 4])
 @pytest.mark.parametrize("dim,n_keep", [(2, 1024), (2, 777), (3, 4099)])
-def test_step_bwd_matches_oracle(dim, n_keep):
+def test_step_bwd_matches_oracle(dim, n_keep, lanes):
     sc = _case(dim, n_keep)
-    log(f"[step_bwd] dim={dim} N={sc.n_particles}")
+    log(f"[step_bwd] dim={dim} N={sc.n_particles} lanes={lanes}")
     S = 2 * dim + 2 * dim * dim
     gout = np.random.default_rng(3).normal(size=(sc.n_particles, S))
     gx, gv, gC, gF = orc.unpack(gout, dim)
-    sim = rt.Simulator.for_scene(sc)
+    sim = rt.Simulator.for_scene(sc, knobs={"lanes": lanes})
     p = rt.params_for_scene(sc)
     s_in = rt.state_for_scene(sc)
     og = rt.State.from_particle_major(gx, gv, gC, gF)
