@@ -46,6 +46,7 @@ enum Region {
   R_GE,        // n_scenes double
   R_GACT,      // kMaxAct double (single-step adjoint)
   R_ERR,       // 1 uint32
+  R_BLOCKS,    // int4 per workgroup: scene-aligned particle ranges
   R_COUNT
 };
 
@@ -72,6 +73,7 @@ struct mpm_ctx {
   int rotate = 1;
   int lanes = 1;
   int graph = 1;
+  int n_blocks = 0;  // workgroups per particle pass for the current block and lanes
   hipStream_t capture = nullptr;
   // Per-kernel timing (knob "timing"): event pairs around each step-kernel
   // launch, read back by mpm_kernel_stats.
@@ -166,6 +168,8 @@ StepConsts consts(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
   k.remap = c.remap;
   k.rotate = c.rotate;
   k.scene_id = c.ns > 1 ? c.at<int>(R_SCENE_ID) : nullptr;
+  k.blocks = c.ns > 1 ? c.at<int4>(R_BLOCKS) : nullptr;
+  k.n_blocks = c.n_blocks;
   k.E = p->E;
   k.nu = p->nu;
   k.vol = p->vol;
@@ -225,7 +229,7 @@ struct Timed {
 template <int D, int LPP>
 mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& a, hipStream_t st) {
   Timed t(c, 0, st);
-  hipLaunchKernelGGL((mpm::k_fwd<D, LPP>), dim3(c.blocks_for(long(c.N) * LPP)), dim3(c.block), 0, st, a);
+  hipLaunchKernelGGL((mpm::k_fwd<D, LPP>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
   LAUNCH_TRY();
   return MPM_OK;
 }
@@ -233,7 +237,7 @@ mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& a, hipStream_t st) {
 template <int D, int LPP>
 mpm_status launch_bwd(const mpm_ctx& c, const BwdArgs& a, hipStream_t st) {
   Timed t(c, 1, st);
-  const int nb = c.blocks_for(long(c.N) * LPP) * (a.split_c ? 2 : 1);
+  const int nb = c.n_blocks * (a.split_c ? 2 : 1);
   hipLaunchKernelGGL((mpm::k_bwd<D, LPP>), dim3(nb), dim3(c.block), 0, st, a);
   LAUNCH_TRY();
   return MPM_OK;
@@ -366,6 +370,26 @@ mpm_status ensure_state(mpm_tape& tp, const mpm_params* p, int step, hipStream_t
   return run_forward(tp, p, t0, t1, s);
 }
 
+// Workgroup table for the current block size and lanes: one scene per
+// workgroup when there are several scenes (uploaded to R_BLOCKS), else plain
+// ceil(N / particles per workgroup).
+mpm_status update_blocks(mpm_ctx& c) {
+  const int per_block = c.block / c.lanes;
+  if (c.ns <= 1) {
+    c.n_blocks = (c.N + per_block - 1) / per_block;
+    return MPM_OK;
+  }
+  std::vector<int4> t;
+  for (int sc = 0; sc < c.ns; ++sc)
+    for (int f = c.offsets[sc]; f < c.offsets[sc + 1]; f += per_block)
+      t.push_back(make_int4(f, std::min(per_block, c.offsets[sc + 1] - f), sc, 0));
+  if (t.empty()) t.push_back(make_int4(0, 0, 0, 0));
+  if (t.size() * sizeof(int4) > c.bytes[R_BLOCKS]) return MPM_E_CAPACITY;
+  c.n_blocks = int(t.size());
+  if (c.ws) HIP_TRY(hipMemcpy(c.at<int4>(R_BLOCKS), t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
+  return MPM_OK;
+}
+
 bool same_params(const mpm_params& a, const mpm_params* b) {
   return a.E == b->E && a.nu == b->nu && a.vol == b->vol && a.rho == b->rho && a.act_id == b->act_id &&
          a.act == b->act;
@@ -449,12 +473,15 @@ mpm_status mpm_init(const mpm_desc* desc, mpm_ctx** out) {
   c->bytes[R_GE] = size_t(c->ns) * sizeof(double);
   c->bytes[R_GACT] = size_t(mpm::kMaxAct) * sizeof(double);
   c->bytes[R_ERR] = sizeof(unsigned);
+  // At least 16 particles per workgroup (64 threads, 4 lanes each).
+  c->bytes[R_BLOCKS] = (c->ns > 1) ? (N / 16 + size_t(c->ns) + 1) * sizeof(int4) : 0;
   size_t o = 0;
   for (int r = 0; r < R_COUNT; ++r) {
     c->off[r] = o;
     o = align_up(o + c->bytes[r]);
   }
   c->ws_bytes = o;
+  update_blocks(*c);  // host-side count only (no workspace yet)
   *out = c;
   return MPM_OK;
 }
@@ -480,7 +507,7 @@ mpm_status mpm_bind_workspace(mpm_ctx* ctx, void* dev, size_t bytes) {
   HIP_TRY(hipMemcpy(ctx->at<int>(R_OFFSETS), ctx->offsets.data(), ctx->offsets.size() * sizeof(int),
                     hipMemcpyHostToDevice));
   HIP_TRY(hipMemset(ctx->at<unsigned>(R_ERR), 0, sizeof(unsigned)));
-  return MPM_OK;
+  return update_blocks(*ctx);
 }
 
 mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value) {
@@ -489,7 +516,7 @@ mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value) {
   if (k == "block") {
     if (value != 64 && value != 128 && value != 256) return MPM_E_ARG;
     ctx->block = int(value);
-    return MPM_OK;
+    return update_blocks(*ctx);
   }
   if (k == "lds") {
     if (value != 0 && value != 1) return MPM_E_ARG;
@@ -499,7 +526,7 @@ mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value) {
   if (k == "lanes") {
     if (value != 1 && value != 4) return MPM_E_ARG;
     ctx->lanes = int(value);
-    return MPM_OK;
+    return update_blocks(*ctx);
   }
   if (k == "rotate") {
     if (value != 0 && value != 1) return MPM_E_ARG;

@@ -20,10 +20,18 @@
 // one workgroup cover a small box of nodes. Each phase computes that box
 // (block-wide min/max of the stencil bases); when it fits kTileMax nodes and
 // the workgroup holds one scene, gathers read the box once into LDS and
-// scatters accumulate in LDS (ds_add_f32) and flush each non-zero node to HBM
-// with one hardware FP32 atomic per component. Otherwise the phase reads and
-// scatters global memory directly. Per-scene dL/dE and per-actuator dL/da are
-// reduced per wavefront and added in FP64.
+// scatters accumulate in LDS and flush each non-zero node to HBM with one
+// hardware FP32 atomic per component. Otherwise the phase reads and scatters
+// global memory directly. Per-scene dL/dE and per-actuator dL/da are reduced
+// per wavefront and added in FP64.
+//
+// LDS scatters accumulate in 64-bit fixed point with integer LDS atomics
+// (ds_add_u64): on gfx950 ds_add_f32 sustains ~0.3 lane-ops per clock per CU
+// against ~14 for ds_add_u32. Each workgroup reduces a bound B on |contribution|
+// over its particles and uses the scale 2^e with count * B < 2^(62 - e), so no
+// node sum can overflow and the rounding error per node stays below
+// count * B * 2^-62 (finer than FP32 accumulation); the flush converts each
+// node back to float once.
 #pragma once
 
 #include <climits>
@@ -45,6 +53,8 @@ struct StepConsts {
   int rotate;     // 1: per-lane stencil visiting order (Sten, lane_color)
   float dx, inv_dx, dt, gdt, kappa, act_strength;
   const int* scene_id;  // [N] scene of each particle, or null (one scene)
+  const int4* blocks;   // [n_blocks] scene-aligned workgroups (first, count, scene), or null
+  int n_blocks;         // workgroups per particle pass
   const float* E;
   const float* nu;
   const float* vol;
@@ -200,6 +210,27 @@ __device__ __forceinline__ void quad_reduce(float (&v)[N][M]) {
   }
 }
 
+// v * 2^e rounded to the nearest integer, from the float's bits (integer ops
+// only). Callers guarantee |v| * 2^e < 2^62.
+__device__ __forceinline__ long long to_fixed(float v, int e) {
+  const unsigned bits = __float_as_uint(v);
+  const int ex = int((bits >> 23) & 0xFFu);
+  const unsigned long long mant = (unsigned long long)((bits & 0x7FFFFFu) | 0x800000u);
+  const int sh = ex - 150 + e;  // |v| 2^e = mant * 2^sh
+  const int up = min(max(sh, 0), 63);
+  const int dn = min(max(-sh, 0), 63);
+  const unsigned long long half = dn > 0 ? (1ull << (dn - 1)) : 0ull;
+  unsigned long long m = sh >= 0 ? (mant << up) : ((mant + half) >> dn);
+  m = (ex == 0) ? 0ull : m;  // zero and denormals
+  return (bits >> 31) ? -(long long)m : (long long)m;
+}
+
+__device__ __forceinline__ float from_fixed(long long q, int e) {
+  const double hi = double(int(q >> 32)) * 4294967296.0;
+  const double lo = double(unsigned(q & 0xFFFFFFFFll));
+  return float(ldexp(hi + lo, -e));
+}
+
 // Quad mode: lane `sub` (0..2) of a particle's quad keeps visited node `sub`
 // of axis 0 as its slab; lane 3 keeps a zero-weight slab (it only takes part
 // in the quad reductions).
@@ -234,6 +265,7 @@ struct Tile {
   int ext[D];
   int n;
   bool on;
+  int e;  // fixed-point exponent of a scatter tile
 };
 
 // Node addressing: a box of the scene's grid staged in LDS (L = true), or the
@@ -304,6 +336,38 @@ __device__ __forceinline__ Nodes<D, false> global_nodes(const float4* g, int n) 
   return a;
 }
 
+// Scatter target: a box of the scene's grid in LDS, 64-bit fixed point with
+// scale 2^e, component c of tile node q at tile[c * kTileMax + q].
+template <int D>
+struct FixNodes {
+  long long* p;
+  int lo[D], ext[D];
+  int e;
+  __device__ __forceinline__ int idx(const Sten<D>& st, int o0, int o1, int o2) const {
+    if constexpr (D == 2) {
+      return (st.nc[0][o0] - lo[0]) * ext[1] + (st.nc[1][o1] - lo[1]);
+    } else {
+      return ((st.nc[0][o0] - lo[0]) * ext[1] + (st.nc[1][o1] - lo[1])) * ext[2] + (st.nc[2][o2] - lo[2]);
+    }
+  }
+  __device__ __forceinline__ void add(int q, int c, float v) const {
+    atomicAdd(reinterpret_cast<unsigned long long*>(p + c * kTileMax + q), (unsigned long long)to_fixed(v, e));
+  }
+};
+
+template <int D>
+__device__ __forceinline__ FixNodes<D> fix_nodes(long long* tile, const Tile<D>& T) {
+  FixNodes<D> a;
+  a.p = tile;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    a.lo[q] = T.lo[q];
+    a.ext[q] = T.ext[q];
+  }
+  a.e = T.e;
+  return a;
+}
+
 // Stencil visiting colour of this lane (see Sten): lane mod 3^d, or -1.
 template <int D, int LPP>
 __device__ __forceinline__ int lane_color(const StepConsts& k) {
@@ -339,11 +403,36 @@ __device__ __forceinline__ bool block_one_scene(const StepConsts& k, int first, 
 }
 
 // Block-wide box of the stencil bases of the valid lanes (all threads call).
+// Fixed-point exponent for `count` contributions bounded by `bmax`: the
+// largest e with count * bmax < 2^(62 - e); INT_MIN when the bound is not finite.
+__device__ __forceinline__ int fixed_exponent(float bmax, int count) {
+  const float total = bmax * float(count);
+  if (!(total < 3.0e38f)) return INT_MIN;
+  if (total <= 0.0f) return 0;
+  return 62 - (ilogbf(total) + 1);
+}
+
+// Block-wide max of a non-negative bound (all threads call); returns the
+// fixed-point exponent for `count` contributions of at most that size.
+__device__ __forceinline__ int block_scale(float bound, int count, int* red) {
+  if (threadIdx.x == 0) red[7] = 0;
+  __syncthreads();
+  int b = __float_as_int(bound > 0.0f ? bound : 0.0f);  // non-negative floats order as ints; NaN is largest
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) b = max(b, __shfl_xor(b, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(red + 7, b);
+  __syncthreads();
+  const int e = fixed_exponent(__int_as_float(red[7]), count);
+  __syncthreads();
+  return e;
+}
+
 template <int D>
 __device__ Tile<D> block_tile(bool valid, const int (&base)[D], bool one_scene, int enabled, int* red) {
   Tile<D> T;
   T.on = false;
   T.n = 0;
+  T.e = 0;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     T.lo[a] = 0;
@@ -441,6 +530,48 @@ __device__ __forceinline__ void tile_flush(const Tile<D>& T, const float* tile, 
   }
 }
 
+template <int D, int NC>
+__device__ __forceinline__ void tile_zero64(const Tile<D>& T, long long* tile) {
+  for (int q = threadIdx.x; q < T.n; q += blockDim.x)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) tile[c * kTileMax + q] = 0;
+}
+
+// Adds the non-zero nodes of a fixed-point tile into the global grid.
+template <int D, int NC>
+__device__ __forceinline__ void tile_flush64(const Tile<D>& T, const long long* tile, float4* g, int n) {
+  for (int q = threadIdx.x; q < T.n; q += blockDim.x) {
+    long long v[NC];
+    bool nz = false;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      v[c] = tile[c * kTileMax + q];
+      nz = nz || (v[c] != 0);
+    }
+    if (nz) {
+      float* dst = reinterpret_cast<float*>(g + tile_global_index<D>(T, q, n));
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (v[c] != 0) atomic_add_f32(dst + c, from_fixed(v[c], T.e));
+    }
+  }
+}
+
+// Bound on the size of any scatter contribution w * (m v_c + (A delta)_c) or
+// w * m of a particle (|delta_b| <= 1.5 dx, w <= 1).
+template <int D>
+__device__ __forceinline__ float p2g_bound(float mass, const float (&mv)[D], const float (&A)[D][D], float dx) {
+  float b = mass;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    float s = fabsf(mv[c]);
+#pragma unroll
+    for (int e = 0; e < D; ++e) s += 1.5f * dx * fabsf(A[c][e]);
+    b = fmaxf(b, s);
+  }
+  return b;
+}
+
 // ---------------------------------------------------------------------------
 // Stage bodies (one particle)
 // ---------------------------------------------------------------------------
@@ -503,9 +634,9 @@ __device__ __forceinline__ void g2p_body(const StepConsts& k, const Sten<D>& st,
 }
 
 // p2g: scatter m and P of one particle (A and m v precomputed).
-template <int D, bool L, int S0>
+template <int D, int S0, class SA>
 __device__ __forceinline__ void p2g_body(const StepConsts& k, const Sten<D>& st, float mass, const float (&mv)[D],
-                                         const float (&A)[D][D], const Nodes<D, L>& g) {
+                                         const float (&A)[D][D], const SA& g) {
   for_nodes<D, S0>([&](int o0, int o1, int o2) {
     const float w = wgt<D>(st, o0, o1, o2);
     float dl[D];
@@ -599,10 +730,10 @@ __device__ __forceinline__ void g2p_C(const StepConsts& k, const Sten<D>& st, co
 }
 
 // g2p*: scatter v* into the adjoint grid; accumulate x* (px).
-template <int D, bool L, int S0>
+template <int D, int S0, class GA, class SA>
 __device__ __forceinline__ void g2p_adj_body(const StepConsts& k, const Sten<D>& st, const float (&vt)[D],
-                                             const float (&Bm)[D][D], const Nodes<D, L>& g, const Nodes<D, L>& ad,
-                                             float (&px)[D], bool scatter) {
+                                             const float (&Bm)[D][D], const GA& g, const SA& ad, float (&px)[D],
+                                             bool scatter) {
   float pxa[D] = {};
   for_nodes<D, S0>([&](int o0, int o1, int o2) {
     float v[D];
@@ -650,39 +781,45 @@ __device__ __forceinline__ int actuator_of(const StepConsts& k, const float* act
 // Scatter of one state into `grid` with an optional LDS tile (all threads call).
 template <int D, int LPP>
 __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i, int sc, bool one_scene, int sub,
-                                          const PState<D>& p, const float* act_row, float4* grid, float* tile,
-                                          int* red, unsigned& err) {
+                                          int count, const PState<D>& p, const float* act_row, float4* grid,
+                                          long long* tile, int* red, unsigned& err) {
   constexpr int S0 = (LPP == 4) ? 1 : 3;
   Sten<D> st;
   const bool fin = live && state_finite<D>(p);
   const bool ok = fin && lane_sten<D, LPP>(k, p.x, sub, st);
   if (live && !fin) err |= kErrNonfinite;
   if (fin && !ok) err |= kErrDomain;
-  const Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
-  float4* g = grid + long(sc) * k.nodes;
-  if (T.on) {
-    tile_zero<D, D + 1>(T, tile);
-    __syncthreads();
-  }
+  float A[D][D] = {}, mv[D] = {}, mass = 0.0f, bound = 0.0f;
   if (ok) {
     const SceneParams sp = scene_params(k.E, k.nu, k.vol, k.rho, sc);
     float act_tau;
     actuator_of<D>(k, act_row, i, act_tau);
-    float A[D][D], FFtI[D][D], lnJ, J;
+    float FFtI[D][D], lnJ, J;
     affine<D>(p, sp, act_tau, k.dt, k.kappa, A, FFtI, lnJ, J, err);
-    float mv[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) mv[a] = sp.mass * p.v[a];
-    if (LPP == 1 || sub < 3) {
-      if (T.on)
-        p2g_body<D, true, S0>(k, st, sp.mass, mv, A, lds_nodes<D>(tile, T));
-      else
-        p2g_body<D, false, S0>(k, st, sp.mass, mv, A, global_nodes<D>(g, k.n));
-    }
+    mass = sp.mass;
+    bound = p2g_bound<D>(mass, mv, A, k.dx);
+  }
+  Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
+  if (T.on) {
+    T.e = block_scale(bound, count, red);
+    T.on = T.e != INT_MIN;
+  }
+  float4* g = grid + long(sc) * k.nodes;
+  if (T.on) {
+    tile_zero64<D, D + 1>(T, tile);
+    __syncthreads();
+  }
+  if (ok && (LPP == 1 || sub < 3)) {
+    if (T.on)
+      p2g_body<D, S0>(k, st, mass, mv, A, fix_nodes<D>(tile, T));
+    else
+      p2g_body<D, S0>(k, st, mass, mv, A, global_nodes<D>(g, k.n));
   }
   if (T.on) {
     __syncthreads();
-    tile_flush<D, D + 1>(T, tile, g, k.n);
+    tile_flush64<D, D + 1>(T, tile, g, k.n);
   }
 }
 
@@ -693,13 +830,29 @@ __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i,
 // interleaved, lane_particle). LPP = 4: a quad of lanes per particle; lanes
 // 0..2 each take one slab of the stencil (t0 = 0, 1, 2), lane 3 only joins
 // the quad reductions; lane 0 of the quad writes the particle's outputs.
+//
+// With several scenes, workgroups are scene-aligned: k.blocks[b] = (first
+// particle, particle count, scene) of workgroup b, so every workgroup holds one
+// scene and can stage its grid box in LDS.
 template <int LPP>
 struct LaneMap {
-  int first, i, sub, count;
+  int first, i, sub, count, scene;
   bool live, owner;
   __device__ __forceinline__ LaneMap(const StepConsts& k, int block_index) {
-    count = int(blockDim.x) / LPP;
-    first = block_index * count;
+    const int per_block = int(blockDim.x) / LPP;
+    int end;
+    if (k.blocks) {
+      const int4 bi = k.blocks[block_index];
+      first = bi.x;
+      count = bi.y;
+      scene = bi.z;
+      end = first + count;
+    } else {
+      first = block_index * per_block;
+      count = per_block;
+      scene = 0;
+      end = k.N;
+    }
     if constexpr (LPP == 4) {
       sub = int(threadIdx.x & 3);
       i = first + int(threadIdx.x >> 2);
@@ -707,7 +860,7 @@ struct LaneMap {
       sub = 0;
       i = first + lane_particle(threadIdx.x, blockDim.x, k.remap);
     }
-    live = i < k.N;
+    live = i < end;
     owner = sub == 0;
   }
 };
@@ -715,8 +868,9 @@ struct LaneMap {
 template <int D, int LPP>
 __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   constexpr int S0 = (LPP == 4) ? 1 : 3;
-  __shared__ float tile[4 * kTileMax];
+  __shared__ long long tile64[4 * kTileMax];
   __shared__ int red[8];
+  float* tile = reinterpret_cast<float*>(tile64);
   zero_range(a.clear, a.clear_n);
   const StepConsts& k = a.k;
   const LaneMap<LPP> lm(k, int(blockIdx.x));
@@ -724,8 +878,8 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   const bool live = lm.live;
   // Threads past the end take the scene of the workgroup's first particle:
   // they still load and flush the workgroup's LDS tile.
-  const int sc = k.scene_id ? k.scene_id[live ? i : first] : 0;
-  const bool one_scene = block_one_scene(k, first, lm.count);
+  const int sc = k.blocks ? lm.scene : (k.scene_id ? k.scene_id[live ? i : first] : 0);
+  const bool one_scene = k.blocks ? true : block_one_scene(k, first, lm.count);
   unsigned err = 0;
   PState<D> p;
   if (live) load_state<D>(a.in, i, p);
@@ -749,7 +903,7 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
     }
     if (live && lm.owner) store_state<D>(a.out, i, p);
   }
-  if (a.do_p2g) p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_row, a.grid_out, tile, red, err);
+  if (a.do_p2g) p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_row, a.grid_out, tile64, red, err);
   if (err) atomicOr(k.err, err);
 }
 
@@ -771,29 +925,30 @@ __device__ __forceinline__ void wave_add_keyed(bool live, int key, double val, d
 template <int D, int LPP>
 __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   constexpr int S0 = (LPP == 4) ? 1 : 3;
-  __shared__ float tileA[4 * kTileMax];
-  __shared__ float tileB[4 * kTileMax];
+  __shared__ long long tileA64[4 * kTileMax];
+  __shared__ long long tileB64[4 * kTileMax];
   __shared__ int red[8];
+  float* tileA = reinterpret_cast<float*>(tileA64);
+  float* tileB = reinterpret_cast<float*>(tileB64);
   zero_range(a.clear0, a.clear0_n);
   zero_range(a.clear1, a.clear1_n);
   const StepConsts& k = a.k;
   // With split_c, workgroups [0, nb) run phases A and B and workgroups
   // [nb, 2 nb) run phase C on the same particles: C does not depend on A or B.
-  const int per_block = int(blockDim.x) / LPP;
-  const int nb = (k.N + per_block - 1) / per_block;
+  const int nb = k.n_blocks;
   const bool role_c = a.split_c && int(blockIdx.x) >= nb;
   const LaneMap<LPP> lm(k, role_c ? int(blockIdx.x) - nb : int(blockIdx.x));
   const int first = lm.first, i = lm.i, sub = lm.sub;
   const bool live = lm.live, owner = lm.owner;
   // Threads past the end take the scene of the workgroup's first particle:
   // they still load and flush the workgroup's LDS tile.
-  const int sc = k.scene_id ? k.scene_id[live ? i : first] : 0;
-  const bool one_scene = block_one_scene(k, first, lm.count);
+  const int sc = k.blocks ? lm.scene : (k.scene_id ? k.scene_id[live ? i : first] : 0);
+  const bool one_scene = k.blocks ? true : block_one_scene(k, first, lm.count);
   unsigned err = 0;
   if (role_c) {
     PState<D> p;
     if (live) load_state<D>(a.stC, i, p);
-    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tileA, red, err);
+    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_rowC, a.gC, tileA64, red, err);
     if (err) atomicOr(k.err, err);
     return;
   }
@@ -933,14 +1088,15 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
 #pragma unroll
     for (int c = 0; c < D; ++c) fin = fin && (p.x[c] * 0.0f == 0.0f);
     const bool ok = fin && lane_sten<D, LPP>(k, p.x, sub, st);
-    const Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
+    Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
     const float4* g = a.gB + long(sc) * k.nodes;
     float4* ad = a.aB + long(sc) * k.nodes;
     if (T.on) {
       tile_load<D, D + 1>(T, g, k.n, tileA);
-      tile_zero<D, D>(T, tileB);
+      tile_zero64<D, D>(T, tileB64);
       __syncthreads();
     }
+    float Bm[D][D] = {}, vt[D] = {}, bound = 0.0f;
     if (ok) {
       float Cn[D][D];
       if (a.cnext) {
@@ -954,7 +1110,6 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
         g2p_C<D, false, S0>(k, st, global_nodes<D>(g, k.n), Cn);
       }
       // F' = (I + dt C') F:  F* = (I + dt C')^T F'*,  C'* += dt F'* F^T.
-      float Bm[D][D], vt[D];
 #pragma unroll
       for (int c = 0; c < D; ++c)
 #pragma unroll
@@ -970,16 +1125,32 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
         }
       // x' = x + dt v':  v'* += dt x'*.
 #pragma unroll
-      for (int c = 0; c < D; ++c) vt[c] = gv[c] + k.dt * gx[c];
-      const bool scatter = LPP == 1 || sub < 3;
-      if (T.on)
-        g2p_adj_body<D, true, S0>(k, st, vt, Bm, lds_nodes<D>(tileA, T), lds_nodes<D>(tileB, T), px, scatter);
-      else
-        g2p_adj_body<D, false, S0>(k, st, vt, Bm, global_nodes<D>(g, k.n), global_nodes<D>(ad, k.n), px, scatter);
+      for (int c = 0; c < D; ++c) {
+        vt[c] = gv[c] + k.dt * gx[c];
+        float b = fabsf(vt[c]);
+#pragma unroll
+        for (int e = 0; e < D; ++e) b += 1.5f * k.dx * fabsf(Bm[c][e]);
+        bound = fmaxf(bound, b);
+      }
     }
+    // The scatter tile's scale needs the bound of every particle of the workgroup.
+    bool fix = T.on;
     if (T.on) {
+      T.e = block_scale(bound, lm.count, red);
+      fix = T.e != INT_MIN;
+    }
+    if (ok) {
+      const bool scatter = LPP == 1 || sub < 3;
+      if (T.on && fix)
+        g2p_adj_body<D, S0>(k, st, vt, Bm, lds_nodes<D>(tileA, T), fix_nodes<D>(tileB64, T), px, scatter);
+      else if (T.on)
+        g2p_adj_body<D, S0>(k, st, vt, Bm, lds_nodes<D>(tileA, T), global_nodes<D>(ad, k.n), px, scatter);
+      else
+        g2p_adj_body<D, S0>(k, st, vt, Bm, global_nodes<D>(g, k.n), global_nodes<D>(ad, k.n), px, scatter);
+    }
+    if (T.on && fix) {
       __syncthreads();
-      tile_flush<D, D>(T, tileB, ad, k.n);
+      tile_flush64<D, D>(T, tileB64, ad, k.n);
     }
     if (live && owner) {
 #pragma unroll
@@ -995,7 +1166,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   if (a.do_c && !a.split_c) {
     PState<D> p;
     if (live) load_state<D>(a.stC, i, p);
-    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tileA, red, err);
+    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_rowC, a.gC, tileA64, red, err);
   }
   if (err) atomicOr(k.err, err);
 }
