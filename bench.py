@@ -56,11 +56,21 @@ def _traffic(kernel_name):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def tuned_knobs(scene, args):
+    """Launch configuration from the autotuner (a short trajectory per candidate,
+    cached per workload shape and GPU), or the library defaults."""
+    if args.no_tune:
+        return {}
+    from paper_1910_00935_amd import autotune
+    return autotune.tune(scene, cache=args.tune_cache, steps=min(scene.steps, 64))
+
+
 def run_c3(args, torch, rt, scenes):
     sc = scenes.c3()
     T = sc.steps
     N = sc.n_particles
-    sim = rt.Simulator.for_scene(sc)
+    knobs = tuned_knobs(sc, args)
+    sim = rt.Simulator.for_scene(sc, knobs=knobs)
     params = rt.params_for_scene(sc)
     init = rt.state_for_scene(sc)
     tape = sim.tape(T, 0)
@@ -123,7 +133,7 @@ def run_c3(args, torch, rt, scenes):
                         "alg_bytes_per_launch": v["bytes"]} for k, v in per.items()},
     }
     return {
-        "value": value, "ms_per_step": secs * 1e3 / args.steps, "N": N, "T": T, "roofline": roofline,
+        "value": value, "ms_per_step": secs * 1e3 / args.steps, "N": N, "T": T, "roofline": roofline, "knobs": knobs,
         "whole_step_hbm_frac": round((5 * S * 4 * N * T * args.steps / secs) / (HBM_PEAK_GBS * 1e9), 4),
         "gpu_event_ms": gpu_ms, "wall_s": wall,
     }
@@ -153,9 +163,14 @@ def run_batched(args, torch, rt, scenes, n_scenes=256, steps=256):
     step for all scenes) against one context per scene run back to back."""
     sc = scenes.c5(n_scenes=n_scenes, steps=steps)
     N = sc.n_particles
+    knobs = tuned_knobs(sc, args)
+    # One configuration for every per-scene run, tuned on a median-size scene.
+    counts = [int(sc.offsets[k + 1] - sc.offsets[k]) for k in range(n_scenes)]
+    median = sorted(range(n_scenes), key=lambda k: counts[k])[n_scenes // 2]
+    knobs_one = tuned_knobs(sc.subset([median]), args)
 
-    def make(s):
-        sim = rt.Simulator.for_scene(s)
+    def make(s, kn):
+        sim = rt.Simulator.for_scene(s, knobs=kn)
         p = rt.params_for_scene(s)
         init = rt.state_for_scene(s)
         tape = sim.tape(steps, 0)
@@ -170,14 +185,14 @@ def run_batched(args, torch, rt, scenes, n_scenes=256, steps=256):
             tape.backward(p, seed, g, gE)
         return run, sim
 
-    run, sim = make(sc)
+    run, sim = make(sc, knobs)
     run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run()
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
-    per = [make(sc.subset([k])) for k in range(n_scenes)]
+    per = [make(sc.subset([k]), knobs_one) for k in range(n_scenes)]
     for r, _ in per:
         r()
     torch.cuda.synchronize()
@@ -190,7 +205,8 @@ def run_batched(args, torch, rt, scenes, n_scenes=256, steps=256):
                         f"{steps} steps, fwd+bwd",
             "batched_particle_steps_per_s": N * steps / t_batched,
             "per_scene_particle_steps_per_s": N * steps / t_per,
-            "speedup": t_per / t_batched, "batched_ms": t_batched * 1e3, "per_scene_ms": t_per * 1e3}
+            "speedup": t_per / t_batched, "batched_ms": t_batched * 1e3, "per_scene_ms": t_per * 1e3,
+            "knobs_batched": knobs, "knobs_per_scene": knobs_one}
 
 
 def main():
@@ -201,6 +217,8 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="use the library's default launch configuration")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune.json"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build's path runs on a single MI355X "

@@ -74,3 +74,18 @@ def test_graph_repeated_backward_and_recapture():
     assert rel(fin2.to_particle_major()[0], fin.to_particle_major()[0]) < 1e-6
     assert cos(g.to_particle_major()[1], grads[0][1]) > 0.99999
     assert sim.check_errors() == 0
+
+
+def test_autotune_picks_and_caches(tmp_path):
+    """The autotuner times each candidate, returns one of them, and reuses the
+    cached answer for the same workload shape."""
+    from paper_1910_00935_amd import autotune
+    sc = scenes.c1d().with_steps(8)
+    space = {"block": (128, 64), "lanes": (1, 4), "rotate": (1,), "lds": (1,), "split": (1,)}
+    cache = str(tmp_path / "tune.json")
+    best = autotune.tune(sc, cache=cache, space=space)
+    assert best in autotune.candidates(space)
+    again = autotune.tune(sc, cache=cache, space={"block": (256,)})  # cached: space not searched again
+    assert again == best
+    g = rt.Simulator.for_scene(sc, knobs=best)
+    assert g.N == sc.n_particles
