@@ -42,23 +42,27 @@ def _source_hash():
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel_name):
+def _traffic(kernel_name, knobs):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources; else None."""
+    taken on the current kernel sources with the same launch configuration;
+    else None."""
     try:
         with open(PROFILE_TRAFFIC) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("source_hash") != _source_hash():
+    if rec.get("source_hash") != _source_hash() or rec.get("knobs") != knobs:
         return None
     k = rec.get("kernels", {}).get(kernel_name)
     return None if k is None else k.get("bytes_per_launch")
 
 
-def tuned_knobs(scene, args):
-    """Launch configuration from the autotuner (a short trajectory per candidate,
-    cached per workload shape and GPU), or the library defaults."""
+def tuned_knobs(scene, args, pinned=None):
+    """Launch configuration: `pinned` when given, else the autotuner's (a short
+    trajectory per candidate, cached per workload shape and GPU), or the library
+    defaults with --no-tune."""
+    if pinned:
+        return dict(pinned)
     if args.no_tune:
         return {}
     from paper_1910_00935_amd import autotune
@@ -69,7 +73,7 @@ def run_c3(args, torch, rt, scenes):
     sc = scenes.c3()
     T = sc.steps
     N = sc.n_particles
-    knobs = tuned_knobs(sc, args)
+    knobs = tuned_knobs(sc, args, json.loads(args.knobs) if args.knobs else None)
     sim = rt.Simulator.for_scene(sc, knobs=knobs)
     params = rt.params_for_scene(sc)
     init = rt.state_for_scene(sc)
@@ -127,7 +131,7 @@ def run_c3(args, torch, rt, scenes):
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
     roofline = {
         "bound": "hbm", "kernel": dom_name + "<3>", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(dom_name),
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(dom_name, knobs),
         "bytes_per_launch": dom["bytes"], "mean_launch_us": round(dom["ms"] * 1e3, 3),
         "kernels": {k: {"mean_launch_us": round(v["ms"] * 1e3, 3), "launches": v["launches"],
                         "alg_bytes_per_launch": v["bytes"]} for k, v in per.items()},
@@ -137,6 +141,63 @@ def run_c3(args, torch, rt, scenes):
         "whole_step_hbm_frac": round((5 * S * 4 * N * T * args.steps / secs) / (HBM_PEAK_GBS * 1e9), 4),
         "gpu_event_ms": gpu_ms, "wall_s": wall,
     }
+
+
+COPY_MIB = 64  # calibration copy: reads and writes exactly this many MiB
+
+
+def calibration_copy(torch):
+    """One plain device-to-device copy of COPY_MIB MiB, whose counters give the
+    scale from FETCH_SIZE / WRITE_SIZE readings to bytes."""
+    src = torch.ones(COPY_MIB * 1024 * 1024 // 4, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def _pmc_means(csv_path, counter):
+    """Mean value of `counter` per dispatch for each kernel (short name), and
+    the largest single reading of the copy kernel."""
+    import csv
+    sums, counts, copy_max = {}, {}, 0.0
+    with open(csv_path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"])
+            name = r["Kernel_Name"]
+            if "copyBuffer" in name:
+                copy_max = max(copy_max, v)
+            short = name.split("(")[0].split("::")[-1].split("<")[0]
+            sums[short] = sums.get(short, 0.0) + v
+            counts[short] = counts.get(short, 0) + 1
+    return {k: sums[k] / counts[k] for k in sums}, counts, copy_max
+
+
+def summarize_pmc(fetch_csv, write_csv, knobs, command):
+    """profiles/traffic_c3.json from a FETCH_SIZE run and a WRITE_SIZE run of
+    `bench.py --profile`: per-dispatch KiB of the step kernels, each scaled by
+    the ratio of the calibration copy's known size to its own reading."""
+    fetch, n_f, copy_f = _pmc_means(fetch_csv, "FETCH_SIZE")
+    write, n_w, copy_w = _pmc_means(write_csv, "WRITE_SIZE")
+    known_kib = COPY_MIB * 1024.0
+    sf = known_kib / copy_f if copy_f > 0 else None
+    sw = known_kib / copy_w if copy_w > 0 else None
+    kernels = {}
+    for k in ("k_fwd", "k_bwd"):
+        if k in fetch and k in write and sf and sw:
+            rd = fetch[k] * sf * 1024.0
+            wr = write[k] * sw * 1024.0
+            kernels[k] = {"fetch_kib_raw": fetch[k], "write_kib_raw": write[k], "dispatches": [n_f[k], n_w[k]],
+                          "read_bytes": round(rd), "write_bytes": round(wr), "bytes_per_launch": round(rd + wr)}
+    rec = {"source_hash": _source_hash(), "knobs": knobs, "command": command,
+           "calibration": {"copy_mib": COPY_MIB, "fetch_kib_raw": copy_f, "write_kib_raw": copy_w,
+                           "fetch_scale": sf, "write_scale": sw},
+           "kernels": kernels}
+    with open(PROFILE_TRAFFIC, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
 
 
 def run_cpu_baseline(sample_steps):
@@ -219,7 +280,16 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default launch configuration")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune.json"))
+    ap.add_argument("--knobs", default=None, help='launch configuration for the 3D workload as JSON, e.g. \'{"block": 256}\'')
+    ap.add_argument("--profile", action="store_true",
+                    help="3D workload only, then one calibration copy (for rocprofv3 counter runs)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic record from two rocprofv3 --pmc runs of --profile")
+    ap.add_argument("--pmc-command", default="", help="command recorded with --summarize-pmc")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, json.loads(args.knobs) if args.knobs else {}, args.pmc_command)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build's path runs on a single MI355X "
               f"(--gpus {args.gpus} is not supported)", file=sys.stderr)
@@ -245,6 +315,11 @@ def main():
         "roofline": c3["roofline"],
         "whole_step_hbm_frac": c3["whole_step_hbm_frac"],
     }
+    out["config"]["knobs"] = c3["knobs"]
+    if args.profile:
+        calibration_copy(torch)
+        print(json.dumps(out), flush=True)
+        return
     if not args.no_batched:
         print("[bench] batched 2D workload", flush=True)
         out["batched"] = run_batched(args, torch, rt, scenes)
