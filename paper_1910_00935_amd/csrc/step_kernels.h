@@ -210,19 +210,14 @@ __device__ __forceinline__ void quad_reduce(float (&v)[N][M]) {
   }
 }
 
-// v * 2^e rounded to the nearest integer, from the float's bits (integer ops
-// only). Callers guarantee |v| * 2^e < 2^62.
+// v * 2^e rounded to the nearest integer (ties to even). Callers guarantee
+// |v| * 2^e < 2^62, so the scaled value, its rounding and the split into two
+// 32-bit words are all exact in double precision.
 __device__ __forceinline__ long long to_fixed(float v, int e) {
-  const unsigned bits = __float_as_uint(v);
-  const int ex = int((bits >> 23) & 0xFFu);
-  const unsigned long long mant = (unsigned long long)((bits & 0x7FFFFFu) | 0x800000u);
-  const int sh = ex - 150 + e;  // |v| 2^e = mant * 2^sh
-  const int up = min(max(sh, 0), 63);
-  const int dn = min(max(-sh, 0), 63);
-  const unsigned long long half = dn > 0 ? (1ull << (dn - 1)) : 0ull;
-  unsigned long long m = sh >= 0 ? (mant << up) : ((mant + half) >> dn);
-  m = (ex == 0) ? 0ull : m;  // zero and denormals
-  return (bits >> 31) ? -(long long)m : (long long)m;
+  const double d = rint(ldexp(double(v), e));
+  const double hi = floor(ldexp(d, -32));
+  const unsigned lo = unsigned(fma(hi, -4294967296.0, d));  // d - hi 2^32, in [0, 2^32)
+  return (long long)(((unsigned long long)unsigned(int(hi)) << 32) | lo);
 }
 
 __device__ __forceinline__ float from_fixed(long long q, int e) {
@@ -504,6 +499,29 @@ __device__ __forceinline__ void tile_load(const Tile<D>& T, const float4* g, int
   }
 }
 
+// Scene-grid coordinates of tile node q; returns its linear index.
+template <int D>
+__device__ __forceinline__ int tile_node(const Tile<D>& T, int q, int n, int (&c)[D]) {
+  int r = q;
+#pragma unroll
+  for (int a = D - 1; a >= 0; --a) {
+    c[a] = T.lo[a] + r % T.ext[a];
+    r /= T.ext[a];
+  }
+  int g = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) g = g * n + c[a];
+  return g;
+}
+
+template <int D>
+__device__ __forceinline__ bool tile_node_interior(const int (&c)[D], int n, int bound) {
+  bool in = true;
+#pragma unroll
+  for (int a = 0; a < D; ++a) in = in && interior1(c[a], n, bound);
+  return in;
+}
+
 template <int D, int NC>
 __device__ __forceinline__ void tile_zero(const Tile<D>& T, float* tile) {
   for (int q = threadIdx.x; q < T.n; q += blockDim.x)
@@ -577,15 +595,36 @@ __device__ __forceinline__ float p2g_bound(float mass, const float (&mv)[D], con
 // ---------------------------------------------------------------------------
 
 // Node velocity after the grid update, from (m, P).
+// grid_op at one node: v = P / m + dt g (gravity on axis 1) at active nodes,
+// zero elsewhere (empty nodes and the sticky boundary band).
 template <int D>
-__device__ __forceinline__ void node_velocity(const StepConsts& k, const Sten<D>& st, int o0, int o1, int o2,
-                                              float4 g, float (&v)[D]) {
-  const bool act = node_active<D>(st, o0, o1, o2, k.n, k.bound, g.x);
+__device__ __forceinline__ void grid_vel(bool act, float4 g, float gdt, float (&v)[D]) {
   const float P[3] = {g.y, g.z, g.w};
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    float va = P[a] / g.x + (a == 1 ? k.gdt : 0.0f);
+    float va = P[a] / g.x + (a == 1 ? gdt : 0.0f);
     v[a] = act ? va : 0.0f;
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void node_velocity(const StepConsts& k, const Sten<D>& st, int o0, int o1, int o2,
+                                              float4 g, float (&v)[D]) {
+  grid_vel<D>(node_active<D>(st, o0, o1, o2, k.n, k.bound, g.x), g, k.gdt, v);
+}
+
+// Grid velocity of a visited node: read from a velocity tile (L), or computed
+// from the node's (m, P) in the global grid.
+template <int D, bool L>
+__device__ __forceinline__ void node_vel(const StepConsts& k, const Sten<D>& st, int o0, int o1, int o2,
+                                         const Nodes<D, L>& g, float (&v)[D]) {
+  if constexpr (L) {
+    const float4 t = g.template get<D>(st, o0, o1, o2);
+    v[0] = t.x;
+    v[1] = t.y;
+    if constexpr (D == 3) v[2] = t.z;
+  } else {
+    node_velocity<D>(k, st, o0, o1, o2, g.template get<D + 1>(st, o0, o1, o2), v);
   }
 }
 
@@ -597,7 +636,7 @@ __device__ __forceinline__ void g2p_body(const StepConsts& k, const Sten<D>& st,
     const float w = wgt<D>(st, o0, o1, o2);
     float dl[D], v[D];
     delta<D>(st, o0, o1, o2, k.dx, dl);
-    node_velocity<D>(k, st, o0, o1, o2, g.template get<D + 1>(st, o0, o1, o2), v);
+    node_vel<D>(k, st, o0, o1, o2, g, v);
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       vn[c] += w * v[c];
@@ -653,6 +692,77 @@ __device__ __forceinline__ void p2g_body(const StepConsts& k, const Sten<D>& st,
   });
 }
 
+// grid_op* at one node: from the node's (m, P) and the adjoint v* of its
+// velocity, P* = v* / m and m* = -(v* . P) / m^2 (both zero at inactive nodes).
+template <int D>
+__device__ __forceinline__ void grid_adj(bool act, float4 gm, float4 vb4, float (&Pb)[D], float& mb) {
+  const float inv_m = act ? 1.0f / gm.x : 0.0f;
+  const float P[3] = {gm.y, gm.z, gm.w};
+  const float V[3] = {vb4.x, vb4.y, vb4.z};
+  float vP = 0.0f;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    Pb[c] = V[c] * inv_m;
+    vP += V[c] * P[c];
+  }
+  mb = -vP * inv_m * inv_m;
+}
+
+// P* and m* of a visited node: read from an adjoint tile (L: P* in components
+// 0..D-1, m* in component D; `ad` unused), or computed from the global grid
+// and adjoint grid.
+template <int D, bool L>
+__device__ __forceinline__ void node_adj(const StepConsts& k, const Sten<D>& st, int o0, int o1, int o2,
+                                         const Nodes<D, L>& g, const Nodes<D, L>& ad, float (&Pb)[D], float& mb) {
+  if constexpr (L) {
+    const float4 t = g.template get<D + 1>(st, o0, o1, o2);
+    Pb[0] = t.x;
+    Pb[1] = t.y;
+    if constexpr (D == 3) {
+      Pb[2] = t.z;
+      mb = t.w;
+    } else {
+      mb = t.z;
+    }
+  } else {
+    const float4 gm = g.template get<D + 1>(st, o0, o1, o2);
+    const float4 vb4 = ad.template get<D>(st, o0, o1, o2);
+    grid_adj<D>(node_active<D>(st, o0, o1, o2, k.n, k.bound, gm.x), gm, vb4, Pb, mb);
+  }
+}
+
+// Velocity tile: grid_op applied once per node of the box as it is staged
+// (components 0..D-1 = v), so gathers read v instead of forming P / m per visit.
+template <int D>
+__device__ __forceinline__ void tile_load_vel(const StepConsts& k, const Tile<D>& T, const float4* g, float* tile) {
+  for (int q = threadIdx.x; q < T.n; q += blockDim.x) {
+    int c[D];
+    const float4 gm = g[tile_node<D>(T, q, k.n, c)];
+    float v[D];
+    grid_vel<D>(tile_node_interior<D>(c, k.n, k.bound) && gm.x > 0.0f, gm, k.gdt, v);
+#pragma unroll
+    for (int a = 0; a < D; ++a) tile[a * kTileMax + q] = v[a];
+  }
+}
+
+// Adjoint tile: grid_op* applied once per node of the box (components 0..D-1
+// = P*, component D = m*), from the grid (m, P) and the adjoint grid (v*).
+template <int D>
+__device__ __forceinline__ void tile_load_adj(const StepConsts& k, const Tile<D>& T, const float4* g,
+                                              const float4* ad, float* tile) {
+  for (int q = threadIdx.x; q < T.n; q += blockDim.x) {
+    int c[D];
+    const int gi = tile_node<D>(T, q, k.n, c);
+    const float4 gm = g[gi];
+    const float4 vb4 = ad[gi];
+    float Pb[D], mb;
+    grid_adj<D>(tile_node_interior<D>(c, k.n, k.bound) && gm.x > 0.0f, gm, vb4, Pb, mb);
+#pragma unroll
+    for (int a = 0; a < D; ++a) tile[a * kTileMax + q] = Pb[a];
+    tile[D * kTileMax + q] = mb;
+  }
+}
+
 // p2g* with grid_op* folded in: accumulates into gx, gv, Abar from grid (m, P)
 // and adjoint grid (v*).
 template <int D, bool L, int S0>
@@ -661,20 +771,8 @@ __device__ __forceinline__ void p2g_adj_body(const StepConsts& k, const Sten<D>&
                                              float (&gx)[D], float (&vb)[D], float (&Abar)[D][D]) {
   float gxa[D] = {};
   for_nodes<D, S0>([&](int o0, int o1, int o2) {
-    const float4 gm = g.template get<D + 1>(st, o0, o1, o2);
-    const float4 vb4 = ad.template get<D>(st, o0, o1, o2);
-    const bool act = node_active<D>(st, o0, o1, o2, k.n, k.bound, gm.x);
-    const float inv_m = act ? 1.0f / gm.x : 0.0f;
-    const float P[3] = {gm.y, gm.z, gm.w};
-    const float V[3] = {vb4.x, vb4.y, vb4.z};
-    float Pb[D];
-    float vP = 0.0f;
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-      Pb[c] = V[c] * inv_m;
-      vP += V[c] * P[c];
-    }
-    const float mb = -vP * inv_m * inv_m;
+    float Pb[D], mb;
+    node_adj<D>(k, st, o0, o1, o2, g, ad, Pb, mb);
     const float w = wgt<D>(st, o0, o1, o2);
     float dw[D], dl[D];
     dwgt<D>(st, o0, o1, o2, k.inv_dx, dw);
@@ -716,7 +814,7 @@ __device__ __forceinline__ void g2p_C(const StepConsts& k, const Sten<D>& st, co
     const float w = wgt<D>(st, o0, o1, o2);
     float dl[D], v[D];
     delta<D>(st, o0, o1, o2, k.dx, dl);
-    node_velocity<D>(k, st, o0, o1, o2, g.template get<D + 1>(st, o0, o1, o2), v);
+    node_vel<D>(k, st, o0, o1, o2, g, v);
 #pragma unroll
     for (int c = 0; c < D; ++c)
 #pragma unroll
@@ -737,7 +835,7 @@ __device__ __forceinline__ void g2p_adj_body(const StepConsts& k, const Sten<D>&
   float pxa[D] = {};
   for_nodes<D, S0>([&](int o0, int o1, int o2) {
     float v[D];
-    node_velocity<D>(k, st, o0, o1, o2, g.template get<D + 1>(st, o0, o1, o2), v);
+    node_vel<D>(k, st, o0, o1, o2, g, v);
     const float w = wgt<D>(st, o0, o1, o2);
     float dw[D], dl[D];
     dwgt<D>(st, o0, o1, o2, k.inv_dx, dw);
@@ -890,7 +988,7 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
     const Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
     const float4* g = a.grid_in + long(sc) * k.nodes;
     if (T.on) {
-      tile_load<D, D + 1>(T, g, k.n, tile);
+      tile_load_vel<D>(k, T, g, tile);
       __syncthreads();
     }
     if (ok) {
@@ -929,7 +1027,6 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   __shared__ long long tileB64[4 * kTileMax];
   __shared__ int red[8];
   float* tileA = reinterpret_cast<float*>(tileA64);
-  float* tileB = reinterpret_cast<float*>(tileB64);
   zero_range(a.clear0, a.clear0_n);
   zero_range(a.clear1, a.clear1_n);
   const StepConsts& k = a.k;
@@ -990,8 +1087,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     const float4* g = a.gA + long(sc) * k.nodes;
     const float4* ad = a.aA + long(sc) * k.nodes;
     if (T.on) {
-      tile_load<D, D + 1>(T, g, k.n, tileA);
-      tile_load<D, D>(T, ad, k.n, tileB);
+      tile_load_adj<D>(k, T, g, ad, tileA);
       __syncthreads();
     }
     if (ok) {
@@ -1006,7 +1102,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
       for (int c = 0; c < D; ++c) mv[c] = sp.mass * p.v[c];
       float Abar[D][D] = {}, vb[D] = {};
       if (T.on)
-        p2g_adj_body<D, true, S0>(k, st, sp.mass, mv, A, lds_nodes<D>(tileA, T), lds_nodes<D>(tileB, T), gx, vb,
+        p2g_adj_body<D, true, S0>(k, st, sp.mass, mv, A, lds_nodes<D>(tileA, T), lds_nodes<D>(tileA, T), gx, vb,
                                   Abar);
       else
         p2g_adj_body<D, false, S0>(k, st, sp.mass, mv, A, global_nodes<D>(g, k.n), global_nodes<D>(ad, k.n), gx, vb,
@@ -1092,7 +1188,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     const float4* g = a.gB + long(sc) * k.nodes;
     float4* ad = a.aB + long(sc) * k.nodes;
     if (T.on) {
-      tile_load<D, D + 1>(T, g, k.n, tileA);
+      tile_load_vel<D>(k, T, g, tileA);
       tile_zero64<D, D>(T, tileB64);
       __syncthreads();
     }
