@@ -159,16 +159,18 @@ mpm_status mpm_bind_workspace(mpm_ctx* ctx, void* dev, size_t bytes);
  * "graph" (0/1, default 1:
  * capture each tape forward/backward launch sequence once in a HIP graph on
  * an internal stream and replay it on the caller's stream; the cache is keyed
- * on every pointer the sequence uses); "timing" (0/1: bracket every launch of the two step
- * kernels with HIP events on the launch stream, for mpm_kernel_stats).
+ * on every pointer the sequence uses); "timing" (0/1: bracket every run of consecutive
+ * launches of one step kernel on one stream with a pair of HIP events on that stream, for
+ * mpm_kernel_stats; tape sequences then launch directly instead of replaying a graph).
  * MPM_E_ARG on an unknown key or value. */
 mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value);
 
 /* Step-kernel timing (measurement support, not part of the method): kernel 0
  * is the forward step kernel, 1 the reverse step kernel. Waits for the
- * recorded events, returns the summed duration in ms and the launch count
- * since the previous call for that kernel, and resets them. Requires the
- * "timing" knob; otherwise returns zeros. */
+ * recorded events, returns the summed duration in ms of the timed runs of
+ * that kernel and the number of launches they hold, since the previous call
+ * for that kernel, and resets them. Requires the "timing" knob; otherwise
+ * returns zeros. */
 #define MPM_KERNEL_FWD 0
 #define MPM_KERNEL_BWD 1
 mpm_status mpm_kernel_stats(mpm_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);

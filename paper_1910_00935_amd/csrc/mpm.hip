@@ -47,11 +47,14 @@ enum Region {
   R_GACT,      // kMaxAct double (single-step adjoint)
   R_ERR,       // 1 uint32
   R_BLOCKS,    // int4 per workgroup: scene-aligned particle ranges
+  R_BOXES,     // per grid, 2 int4 per workgroup: nodes its last scatter touched
   R_COUNT
 };
 
 constexpr int kNumGrids = 10;
 constexpr int kGridF = 0, kGridB = 3, kAdj = 7;
+constexpr int kZero = -1, kDirty = -2;
+static_assert(kNumGrids == 10, "mpm_ctx::gstate lists one initial state per grid");
 
 }  // namespace
 
@@ -74,13 +77,28 @@ struct mpm_ctx {
   int lanes = 1;
   int graph = 1;
   int n_blocks = 0;  // workgroups per particle pass for the current block and lanes
+  // What each grid holds, tracked while a launch sequence is enqueued: kZero,
+  // kDirty (anything), or n >= 0: non-zero only inside the boxes its last
+  // scatter (n workgroups) recorded in its R_BOXES table.
+  long box_cap = 0;
+  mutable int gstate[kNumGrids] = {kDirty, kDirty, kDirty, kDirty, kDirty, kDirty, kDirty, kDirty, kDirty, kDirty};
   hipStream_t capture = nullptr;
-  // Per-kernel timing (knob "timing"): event pairs around each step-kernel
-  // launch, read back by mpm_kernel_stats.
+  // Per-kernel timing (knob "timing"): one event pair around each run of
+  // consecutive launches of one step kernel on one stream (a span), read back
+  // by mpm_kernel_stats as total time and launch count.
+  struct Span {
+    int kind;
+    hipEvent_t e0, e1;
+    long n;
+  };
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  std::vector<Span> ev_pending;
   size_t ev_used = 0;
+  int span_kind = -1;
+  long span_n = 0;
+  hipEvent_t span_e0 = nullptr;
+  hipStream_t span_st = nullptr;
   double ev_ms[2] = {0.0, 0.0};
   long ev_count[2] = {0, 0};
 
@@ -158,6 +176,7 @@ StepConsts consts(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
   k.bound = c.bound;
   k.nodes = int(c.nodes);
   k.n_act = c.n_act;
+  k.n_scenes = c.ns;
   k.dx = c.dx;
   k.inv_dx = 1.0f / c.dx;
   k.dt = c.dt;
@@ -183,7 +202,10 @@ const float* act_row(const mpm_ctx& c, const mpm_params* p, int s) {
   return (p->act && c.n_act > 0) ? p->act + size_t(s) * c.n_act : nullptr;
 }
 
+void span_close(const mpm_ctx& cc);
+
 mpm_status zero_f4(const mpm_ctx& c, float4* p, long n, hipStream_t st) {
+  span_close(c);
   const int blocks = int(std::min<long>((n + 255) / 256, 8192));
   if (blocks <= 0) return MPM_OK;
   hipLaunchKernelGGL(mpm::k_zero_f4, dim3(blocks), dim3(256), 0, st, p, n);
@@ -199,6 +221,44 @@ mpm_status zero_f64(double* p, long n, hipStream_t st) {
   return MPM_OK;
 }
 
+// Sparse clears: a scatter into grid g records its workgroups' boxes (when
+// LDS boxes are on) and a later clear of g zeroes only those boxes.
+int4* box_table(const mpm_ctx& c, int g) { return c.at<int4>(R_BOXES) + size_t(g) * 2 * size_t(c.box_cap); }
+
+mpm_status zero_grid(const mpm_ctx& c, int g, hipStream_t s) {
+  c.gstate[g] = kZero;
+  return zero_f4(c, c.grid(g), c.grid_f4(), s);
+}
+
+// Box table for a scatter into grid g (null: not recorded).
+int4* scatter_into(const mpm_ctx& c, int g) {
+  if (c.lds) {
+    c.gstate[g] = c.n_blocks;
+    return box_table(c, g);
+  }
+  c.gstate[g] = kDirty;
+  return nullptr;
+}
+
+// Clear of grid g by a step launch: nothing (already zero), its recorded
+// boxes, or the whole grid.
+void plan_clear(const mpm_ctx& c, int g, float4*& ptr, long& n, const int4*& box, int& nbox) {
+  ptr = nullptr;
+  n = 0;
+  box = nullptr;
+  nbox = 0;
+  if (c.gstate[g] != kZero) {
+    ptr = c.grid(g);
+    if (c.gstate[g] == c.n_blocks) {
+      box = box_table(c, g);
+      nbox = c.n_blocks;
+    } else {
+      n = c.grid_f4();
+    }
+  }
+  c.gstate[g] = kZero;
+}
+
 hipEvent_t pool_event(mpm_ctx& c) {
   if (c.ev_used == c.ev_pool.size()) {
     hipEvent_t e = nullptr;
@@ -208,27 +268,44 @@ hipEvent_t pool_event(mpm_ctx& c) {
   return c.ev_pool[c.ev_used++];
 }
 
-// Brackets one launch with timing events when the "timing" knob is on.
-struct Timed {
-  mpm_ctx& c;
-  int kind;
-  hipStream_t st;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  Timed(const mpm_ctx& cc, int k, hipStream_t s) : c(const_cast<mpm_ctx&>(cc)), kind(k), st(s) {
-    if (c.timing) {
-      e0 = pool_event(c);
-      e1 = pool_event(c);
-      if (e0 && e1 && hipEventRecord(e0, st) != hipSuccess) e0 = e1 = nullptr;
-    }
+// Ends the open timing span (any launch that is not a step kernel, and the
+// end of every entry point, calls this).
+void span_close(const mpm_ctx& cc) {
+  mpm_ctx& c = const_cast<mpm_ctx&>(cc);
+  if (c.span_kind < 0) return;
+  hipEvent_t e1 = pool_event(c);
+  if (e1 && hipEventRecord(e1, c.span_st) == hipSuccess) c.ev_pending.push_back({c.span_kind, c.span_e0, e1, c.span_n});
+  c.span_kind = -1;
+  c.span_n = 0;
+}
+
+// Before a step-kernel launch of `kind` on `s`: extends the open span or opens one.
+void span_step(const mpm_ctx& cc, int kind, hipStream_t s) {
+  mpm_ctx& c = const_cast<mpm_ctx&>(cc);
+  if (!c.timing) return;
+  if (c.span_kind == kind && c.span_st == s) {
+    ++c.span_n;
+    return;
   }
-  ~Timed() {
-    if (e0 && e1 && hipEventRecord(e1, st) == hipSuccess) c.ev_pending.push_back({kind, {e0, e1}});
-  }
+  span_close(c);
+  hipEvent_t e0 = pool_event(c);
+  if (!e0 || hipEventRecord(e0, s) != hipSuccess) return;
+  c.span_kind = kind;
+  c.span_e0 = e0;
+  c.span_st = s;
+  c.span_n = 1;
+}
+
+// Closes the open timing span when an entry point returns.
+struct SpanGuard {
+  const mpm_ctx& c;
+  explicit SpanGuard(const mpm_ctx& cc) : c(cc) {}
+  ~SpanGuard() { span_close(c); }
 };
 
 template <int D, int LPP>
 mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& a, hipStream_t st) {
-  Timed t(c, 0, st);
+  span_step(c, 0, st);
   hipLaunchKernelGGL((mpm::k_fwd<D, LPP>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
   LAUNCH_TRY();
   return MPM_OK;
@@ -236,7 +313,7 @@ mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& a, hipStream_t st) {
 
 template <int D, int LPP>
 mpm_status launch_bwd(const mpm_ctx& c, const BwdArgs& a, hipStream_t st) {
-  Timed t(c, 1, st);
+  span_step(c, 1, st);
   const int nb = c.n_blocks * (a.split_c ? 2 : 1);
   hipLaunchKernelGGL((mpm::k_bwd<D, LPP>), dim3(nb), dim3(c.block), 0, st, a);
   LAUNCH_TRY();
@@ -270,6 +347,7 @@ BwdArgs bwd_args(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
 
 // Sorts particles by (scene, Morton cell) of `st`; writes R_PERM.
 mpm_status sort_particles(const mpm_ctx& c, StateRef st, hipStream_t s) {
+  span_close(c);
   int* counts = c.at<int>(R_COUNTS);
   int* start = c.at<int>(R_START);
   int* bsums = c.at<int>(R_BSUMS);
@@ -305,6 +383,7 @@ mpm_status sort_particles(const mpm_ctx& c, StateRef st, hipStream_t s) {
 }
 
 mpm_status gather_state(const mpm_ctx& c, StateRef src, StateRef dst, const int* perm, hipStream_t s) {
+  span_close(c);
   const int pb = (c.N + 255) / 256;
   if (c.d == 2)
     hipLaunchKernelGGL(mpm::k_gather_state<2>, dim3(pb), dim3(256), 0, s, src, dst, perm, c.N);
@@ -315,6 +394,7 @@ mpm_status gather_state(const mpm_ctx& c, StateRef src, StateRef dst, const int*
 }
 
 mpm_status scatter_state(const mpm_ctx& c, StateRef src, StateRef dst, const int* perm, hipStream_t s) {
+  span_close(c);
   const int pb = (c.N + 255) / 256;
   if (c.d == 2)
     hipLaunchKernelGGL(mpm::k_scatter_state<2>, dim3(pb), dim3(256), 0, s, src, dst, perm, c.N);
@@ -335,10 +415,11 @@ mpm_status scatter_state(const mpm_ctx& c, StateRef src, StateRef dst, const int
 mpm_status run_forward(mpm_tape& tp, const mpm_params* p, int t0, int t1, hipStream_t s) {
   const mpm_ctx& c = *tp.ctx;
   const int* act_id = p->act_id ? c.at<int>(R_ACT_ID) : nullptr;
-  for (int k = 0; k < 3; ++k) TRY(zero_f4(c, c.grid(kGridF + k), c.grid_f4(), s));
+  for (int k = 0; k < 3; ++k) TRY(zero_grid(c, kGridF + k, s));
   FwdArgs a = fwd_args(c, p, act_id);
   a.in = tp.slot(t0);
   a.grid_out = c.grid(kGridF);
+  a.box_out = scatter_into(c, kGridF);
   a.act_row = act_row(c, p, t0);
   a.do_p2g = 1;
   TRY(fwd(c, a, s));
@@ -352,8 +433,11 @@ mpm_status run_forward(mpm_tape& tp, const mpm_params* p, int t0, int t1, hipStr
     b.do_p2g = (t + 1 < t1) ? 1 : 0;
     b.grid_out = c.grid(kGridF + (u + 1) % 3);
     b.act_row = act_row(c, p, t + 1);
-    b.clear = (t + 1 < t1) ? c.grid(kGridF + (u + 2) % 3) : nullptr;
-    b.clear_n = c.grid_f4();
+    if (b.do_p2g) {
+      // Grid (u + 2) % 3 was last read in the previous launch; it is written next launch.
+      plan_clear(c, kGridF + (u + 2) % 3, b.clear, b.clear_n, b.clear_box, b.clear_nbox);
+      b.box_out = scatter_into(c, kGridF + (u + 1) % 3);
+    }
     TRY(fwd(c, b, s));
     if (!tp.full && (t + 1) != tp.T && (t + 1) % tp.K != 0) tp.ring_holds[(t + 1) % (2 * tp.K)] = t + 1;
   }
@@ -475,6 +559,8 @@ mpm_status mpm_init(const mpm_desc* desc, mpm_ctx** out) {
   c->bytes[R_ERR] = sizeof(unsigned);
   // At least 16 particles per workgroup (64 threads, 4 lanes each).
   c->bytes[R_BLOCKS] = (c->ns > 1) ? (N / 16 + size_t(c->ns) + 1) * sizeof(int4) : 0;
+  c->box_cap = long(N / 16 + size_t(c->ns) + 1);
+  c->bytes[R_BOXES] = size_t(kNumGrids) * 2 * size_t(c->box_cap) * sizeof(int4);
   size_t o = 0;
   for (int r = 0; r < R_COUNT; ++r) {
     c->off[r] = o;
@@ -500,6 +586,7 @@ mpm_status mpm_bind_workspace(mpm_ctx* ctx, void* dev, size_t bytes) {
   if (reinterpret_cast<uintptr_t>(dev) % kAlign != 0) return MPM_E_ARG;
   if (bytes < ctx->ws_bytes) return MPM_E_CAPACITY;
   ctx->ws = static_cast<char*>(dev);
+  for (int g = 0; g < kNumGrids; ++g) ctx->gstate[g] = kDirty;
   std::vector<int> sid(size_t(ctx->N));
   for (int k = 0; k < ctx->ns; ++k)
     for (int p = ctx->offsets[k]; p < ctx->offsets[k + 1]; ++p) sid[size_t(p)] = k;
@@ -558,12 +645,13 @@ mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value) {
 
 mpm_status mpm_kernel_stats(mpm_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches) {
   if (!ctx || kernel < 0 || kernel > 1 || !total_ms || !launches) return MPM_E_ARG;
+  span_close(*ctx);
   for (auto& p : ctx->ev_pending) {
-    HIP_TRY(hipEventSynchronize(p.second.second));
+    HIP_TRY(hipEventSynchronize(p.e1));
     float ms = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&ms, p.second.first, p.second.second));
-    ctx->ev_ms[p.first] += ms;
-    ctx->ev_count[p.first] += 1;
+    HIP_TRY(hipEventElapsedTime(&ms, p.e0, p.e1));
+    ctx->ev_ms[p.kind] += ms;
+    ctx->ev_count[p.kind] += p.n;
   }
   ctx->ev_pending.clear();
   ctx->ev_used = 0;
@@ -581,9 +669,11 @@ mpm_status mpm_step_fwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, co
   if (!params_ok(params) || !state_ok(in) || !state_ok(out) || step < 0) return MPM_E_ARG;
   if (in->x == out->x || in->v == out->v || in->C == out->C || in->F == out->F) return MPM_E_ARG;
   const mpm_ctx& c = *ctx;
+  const SpanGuard guard(c);
   hipStream_t s = static_cast<hipStream_t>(stream);
   float4* g = c.grid(kGridB);
   TRY(zero_f4(c, g, c.grid_f4(), s));
+  c.gstate[kGridB] = kDirty;  // written below without a box record
   FwdArgs a = fwd_args(c, params, params->act_id);
   a.in = user_ref(c, in);
   a.grid_out = g;
@@ -605,11 +695,13 @@ mpm_status mpm_step_bwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, co
   if (!params_ok(params) || !state_ok(in) || !state_ok(out_grad) || !state_ok(in_grad) || step < 0)
     return MPM_E_ARG;
   const mpm_ctx& c = *ctx;
+  const SpanGuard guard(c);
   hipStream_t s = static_cast<hipStream_t>(stream);
   float4* g = c.grid(kGridB);
   float4* ad = c.grid(kAdj);
   TRY(zero_f4(c, g, c.grid_f4(), s));
   TRY(zero_f4(c, ad, c.grid_f4(), s));
+  c.gstate[kGridB] = c.gstate[kAdj] = kDirty;  // written below without a box record
   TRY(zero_f64(c.at<double>(R_GE), c.ns, s));
   TRY(zero_f64(c.at<double>(R_GACT), mpm::kMaxAct, s));
   FwdArgs a = fwd_args(c, params, params->act_id);
@@ -640,6 +732,7 @@ mpm_status mpm_step_bwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, co
   e.out = user_ref(c, in_grad);
   e.out_perm = nullptr;
   TRY(bwd(c, e, s));
+  span_close(c);
   if (pg && pg->E) {
     hipLaunchKernelGGL(mpm::k_add_f64_to_f32, dim3((c.ns + 255) / 256), dim3(256), 0, s, c.at<double>(R_GE), pg->E,
                        c.ns);
@@ -709,6 +802,7 @@ mpm_status enqueue_tape_forward(mpm_tape* tape, const mpm_params* params, const 
   const int* perm = c.at<int>(R_PERM);
   TRY(gather_state(c, init_ref, tape->slot(0), perm, s));
   if (params->act_id && c.n_act > 0) {
+    span_close(c);
     hipLaunchKernelGGL(mpm::k_gather_i32, dim3((c.N + 255) / 256), dim3(256), 0, s, params->act_id,
                        c.at<int>(R_ACT_ID), perm, c.N);
     LAUNCH_TRY();
@@ -730,16 +824,19 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
   TRY(gather_state(c, user_ref(c, final_grad), seed, perm, s));
   TRY(zero_f64(c.at<double>(R_GE), c.ns, s));
   TRY(zero_f64(tape->gact(), long(T) * std::max(c.n_act, 1), s));
-  for (int k = kGridB; k < kNumGrids; ++k) TRY(zero_f4(c, c.grid(k), c.grid_f4(), s));
+  for (int k = kGridB; k < kNumGrids; ++k) TRY(zero_grid(c, k, s));
 
-  auto gB = [&](int step) { return c.grid(kGridB + step % 4); };
-  auto aB = [&](int step) { return c.grid(kAdj + step % 3); };
+  auto iB = [](int step) { return kGridB + step % 4; };
+  auto iA = [](int step) { return kAdj + step % 3; };
+  auto gB = [&](int step) { return c.grid(iB(step)); };
+  auto aB = [&](int step) { return c.grid(iA(step)); };
 
   TRY(ensure_state(*tape, params, T - 1, s));
   {
     FwdArgs a = fwd_args(c, params, act_id);
     a.in = tape->slot(T - 1);
     a.grid_out = gB(T - 1);
+    a.box_out = scatter_into(c, iB(T - 1));
     a.act_row = act_row(c, params, T - 1);
     a.do_p2g = 1;
     TRY(fwd(c, a, s));
@@ -767,17 +864,19 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
     b.cnext_stride = nx.stride;
     b.gB = gB(st);
     b.aB = aB(st);
+    // Grid st+2 and adjoint grid st+2 were last read by the previous launch
+    // (phase A); neither is touched by this one.
+    plan_clear(c, iB(st + 2), b.clear0, b.clear0_n, b.clear0_box, b.clear0_nbox);
+    plan_clear(c, iA(st + 2), b.clear1, b.clear1_n, b.clear1_box, b.clear1_nbox);
+    b.boxB = scatter_into(c, iA(st));
     if (st >= 1) {
       b.do_c = 1;
       b.split_c = c.split_c;
       b.stC = tape->slot(st - 1);
       b.act_rowC = act_row(c, params, st - 1);
       b.gC = gB(st - 1);
+      b.boxC = scatter_into(c, iB(st - 1));
     }
-    b.clear0 = gB(st + 2);
-    b.clear0_n = c.grid_f4();
-    b.clear1 = aB(st + 2);
-    b.clear1_n = c.grid_f4();
     TRY(bwd(c, b, s));
   }
   {
@@ -794,6 +893,7 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
     b.out_perm = perm;
     TRY(bwd(c, b, s));
   }
+  span_close(c);
   if (pg && pg->E) {
     hipLaunchKernelGGL(mpm::k_add_f64_to_f32, dim3((c.ns + 255) / 256), dim3(256), 0, s, c.at<double>(R_GE), pg->E,
                        c.ns);
@@ -878,6 +978,7 @@ mpm_status mpm_tape_forward(mpm_tape* tape, const mpm_params* params, const mpm_
   if (!tape->mem) return MPM_E_TAPE;
   if (!tape->ctx->ws) return MPM_E_STATE;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const SpanGuard guard(*tape->ctx);
   tape->recorded = false;
   if (!tape->full) std::fill(tape->ring_holds.begin(), tape->ring_holds.end(), -1);
   TRY(run_graphed(tape, graph_key(tape, 0, params, init, final_state, nullptr), s,
@@ -893,6 +994,7 @@ mpm_status mpm_tape_backward(mpm_tape* tape, const mpm_params* params, const mpm
   if (!tape->mem || !tape->recorded || !same_params(tape->rec, params)) return MPM_E_TAPE;
   if (!tape->ctx->ws) return MPM_E_STATE;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const SpanGuard guard(*tape->ctx);
   return run_graphed(tape, graph_key(tape, 1, params, final_grad, init_grad, pg), s,
                      [&](hipStream_t cs) { return enqueue_tape_backward(tape, params, final_grad, init_grad, pg, cs); });
 }
@@ -908,12 +1010,22 @@ mpm_status mpm_loss(mpm_ctx* ctx, int32_t kind, int32_t axis, float sign, const 
   StateRef sd{nullptr, nullptr, nullptr, nullptr, c.N};
   if (seed) sd = user_ref(c, seed);
   if (c.d == 2)
-    hipLaunchKernelGGL(mpm::k_loss_mean<2>, dim3(c.ns), dim3(256), 0, s, user_ref(c, final_state),
-                       c.at<int>(R_OFFSETS), axis, sign, loss_dev, sd);
+    hipLaunchKernelGGL(mpm::k_loss_mean<2>, dim3(c.ns), dim3(1024), 0, s, user_ref(c, final_state),
+                       c.at<int>(R_OFFSETS), axis, sign, loss_dev);
   else
-    hipLaunchKernelGGL(mpm::k_loss_mean<3>, dim3(c.ns), dim3(256), 0, s, user_ref(c, final_state),
-                       c.at<int>(R_OFFSETS), axis, sign, loss_dev, sd);
+    hipLaunchKernelGGL(mpm::k_loss_mean<3>, dim3(c.ns), dim3(1024), 0, s, user_ref(c, final_state),
+                       c.at<int>(R_OFFSETS), axis, sign, loss_dev);
   LAUNCH_TRY();
+  if (seed && c.N > 0) {
+    const int pb = (c.N + 255) / 256;
+    if (c.d == 2)
+      hipLaunchKernelGGL(mpm::k_loss_seed<2>, dim3(pb), dim3(256), 0, s, c.at<int>(R_OFFSETS), c.ns, c.N, axis, sign,
+                         sd);
+    else
+      hipLaunchKernelGGL(mpm::k_loss_seed<3>, dim3(pb), dim3(256), 0, s, c.at<int>(R_OFFSETS), c.ns, c.N, axis, sign,
+                         sd);
+    LAUNCH_TRY();
+  }
   return MPM_OK;
 }
 

@@ -48,6 +48,7 @@ struct StepConsts {
   int bound;      // sticky band width
   int nodes;      // n^d, nodes per scene
   int n_act;      // actuator columns
+  int n_scenes;
   int lds;        // 1: stage gathers and scatters in LDS when the box fits
   int remap;      // 1: interleave the workgroup's particles across waves (lane_particle)
   int rotate;     // 1: per-lane stencil visiting order (Sten, lane_color)
@@ -71,8 +72,11 @@ struct FwdArgs {
   float4* grid_out;        // grid s+1 (scattered when do_p2g)
   const float* act_row;    // actuation row of the scattered state, or null
   int do_g2p, do_p2g;
-  float4* clear;           // buffer zeroed by this launch, or null
-  long clear_n;            // float4 count
+  float4* clear;           // grid zeroed by this launch, or null
+  long clear_n;            // float4 count (dense clear)
+  const int4* clear_box;   // or: the boxes its last scatter recorded (clear_nbox workgroups)
+  int clear_nbox;
+  int4* box_out;           // box table of grid_out (record_box), or null
 };
 
 struct BwdArgs {
@@ -108,8 +112,14 @@ struct BwdArgs {
   float4* gC;
   float4* clear0;
   long clear0_n;
+  const int4* clear0_box;
+  int clear0_nbox;
   float4* clear1;
   long clear1_n;
+  const int4* clear1_box;
+  int clear1_nbox;
+  int4* boxB;              // box tables of aB and gC (record_box), or null
+  int4* boxC;
 };
 
 // Visits the stencil nodes (t0, t1, t2); S0 = 3 visits all, S0 = 1 only the
@@ -182,6 +192,65 @@ __device__ __forceinline__ void zero_range(float4* p, long n) {
   for (long q = long(blockIdx.x) * blockDim.x + threadIdx.x; q < n; q += stride) p[q] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// (r / d, r % d) for 0 <= r < 2^16 and 1 <= d <= 2^10, with rcp = (1/d)(1 + 2^-20):
+// the product r * rcp then lies in [r/d, floor(r/d) + 1) exactly as in real
+// arithmetic, so its truncation is the quotient.
+__device__ __forceinline__ int div_small(int r, int d, float rcp, int& rem) {
+  const int q = int(float(r) * rcp);
+  rem = r - q * d;
+  return q;
+}
+
+// Sparse clears. A scatter launch records, per workgroup, the box of nodes
+// it may have written (record_box): two int4, (lo_0, lo_1, lo_2, scene) and
+// (ext_0, ext_1, ext_2, 0), scene -1 for every scene, ext_0 = 0 for none. The
+// launch that later clears that grid zeroes the recorded boxes instead of the
+// whole grid; boxes are clamped to the grid.
+template <int D>
+__device__ __forceinline__ void clear_box_nodes(float4* grid, int4 lo, int4 ex, int n, int nodes, int n_scenes) {
+  const int l0 = max(lo.x, 0), l1 = max(lo.y, 0), l2 = (D == 3) ? max(lo.z, 0) : 0;
+  const int e0 = min(lo.x + ex.x, n) - l0, e1 = min(lo.y + ex.y, n) - l1;
+  const int e2 = (D == 3) ? min(lo.z + ex.z, n) - l2 : 1;
+  if (e0 <= 0 || e1 <= 0 || e2 <= 0) return;
+  const int total = e0 * e1 * e2;
+  const bool small = total < 65536 && e1 <= 1024 && e2 <= 1024;
+  const float r1 = small ? (1.0f / float(e1)) * (1.0f + 0x1p-20f) : 0.0f;
+  const float r2 = small ? (1.0f / float(e2)) * (1.0f + 0x1p-20f) : 0.0f;
+  const int s0 = (lo.w >= 0) ? lo.w : 0;
+  const int s1 = (lo.w >= 0) ? min(lo.w + 1, n_scenes) : n_scenes;
+  for (int sc = s0; sc < s1; ++sc) {
+    float4* g = grid + long(sc) * nodes;
+    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+      int c0, c1, c2, r;
+      if (small) {
+        r = div_small(q, e2, r2, c2);
+        c0 = div_small(r, e1, r1, c1);
+      } else {
+        c2 = q % e2;
+        r = q / e2;
+        c1 = r % e1;
+        c0 = r / e1;
+      }
+      const long idx = (D == 3) ? (long(l0 + c0) * n + (l1 + c1)) * n + (l2 + c2) : long(l0 + c0) * n + (l1 + c1);
+      g[idx] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+}
+
+// Clears the boxes of two tables (either may be null), entries distributed
+// over the launch's workgroups.
+template <int D>
+__device__ __forceinline__ void clear_boxes(float4* g0, const int4* t0, int n0, float4* g1, const int4* t1, int n1,
+                                            int n, int nodes, int n_scenes) {
+  const int m0 = t0 ? n0 : 0, m1 = t1 ? n1 : 0;
+  for (int j = blockIdx.x; j < m0 + m1; j += gridDim.x) {
+    const bool first = j < m0;
+    const int4* t = first ? t0 : t1;
+    const int jj = first ? j : j - m0;
+    clear_box_nodes<D>(first ? g0 : g1, t[2 * jj], t[2 * jj + 1], n, nodes, n_scenes);
+  }
+}
+
 __device__ __forceinline__ void atomic_add_f32(float* p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add_f64(double* p, double v) { unsafeAtomicAdd(p, v); }
 
@@ -210,14 +279,18 @@ __device__ __forceinline__ void quad_reduce(float (&v)[N][M]) {
   }
 }
 
-// v * 2^e rounded to the nearest integer (ties to even). Callers guarantee
-// |v| * 2^e < 2^62, so the scaled value, its rounding and the split into two
-// 32-bit words are all exact in double precision.
+// v * 2^e as a 64-bit integer from single-precision operations only (all
+// full rate): the high word is h = round(v 2^(e-32)), the low word the
+// remainder v 2^e - h 2^32, which lies in [-2^31, 2^31] and is exact in
+// single precision; both are converted by truncation. The result is within
+// one unit of v 2^e (within 128 units when v 2^(e-32) lies exactly halfway
+// between two integers). Callers guarantee |v| 2^e < 2^62.
 __device__ __forceinline__ long long to_fixed(float v, int e) {
-  const double d = rint(ldexp(double(v), e));
-  const double hi = floor(ldexp(d, -32));
-  const unsigned lo = unsigned(fma(hi, -4294967296.0, d));  // d - hi 2^32, in [0, 2^32)
-  return (long long)(((unsigned long long)unsigned(int(hi)) << 32) | lo);
+  const float x = ldexpf(v, e);
+  const float hf = rintf(ldexpf(v, e - 32));
+  const float r = fminf(fmaf(-hf, 4294967296.0f, x), 2147483520.0f);  // keep int(r) in range
+  const int hi = int(hf), lo = int(r);
+  return (long long)(((unsigned long long)unsigned(hi + (lo >> 31)) << 32) | unsigned(lo));
 }
 
 __device__ __forceinline__ float from_fixed(long long q, int e) {
@@ -258,10 +331,12 @@ template <int D>
 struct Tile {
   int lo[D];
   int ext[D];
+  float rcp[D];  // 1 / ext, rounded up by ~2^-20 (division-free coordinates, tile_coord)
   int n;
   bool on;
   int e;  // fixed-point exponent of a scatter tile
 };
+
 
 // Node addressing: a box of the scene's grid staged in LDS (L = true), or the
 // scene's global grid. LDS tiles are structure-of-arrays, component c of tile
@@ -432,6 +507,7 @@ __device__ Tile<D> block_tile(bool valid, const int (&base)[D], bool one_scene, 
   for (int a = 0; a < D; ++a) {
     T.lo[a] = 0;
     T.ext[a] = 0;
+    T.rcp[a] = 0.0f;
   }
   if (!enabled) return T;
   const int t = threadIdx.x;
@@ -464,6 +540,7 @@ __device__ Tile<D> block_tile(bool valid, const int (&base)[D], bool one_scene, 
   for (int a = 0; a < D; ++a) {
     T.lo[a] = any ? red[a] : 0;
     T.ext[a] = any ? red[D + a] - red[a] + 3 : 0;
+    T.rcp[a] = any ? (1.0f / float(T.ext[a])) * (1.0f + 0x1p-20f) : 0.0f;
     n *= T.ext[a];
   }
   T.n = n;
@@ -472,18 +549,29 @@ __device__ Tile<D> block_tile(bool valid, const int (&base)[D], bool one_scene, 
   return T;
 }
 
+// Records the box of a scatter's nodes for workgroup `index` (thread 0).
+template <int D>
+__device__ __forceinline__ void record_box(int4* table, int index, const Tile<D>& T, int scene) {
+  if (!table || threadIdx.x != 0) return;
+  const bool any = T.n > 0;
+  table[2 * index] = make_int4(T.lo[0], T.lo[1], D == 3 ? T.lo[2] : 0, scene);
+  table[2 * index + 1] = make_int4(any ? T.ext[0] : 0, any ? T.ext[1] : 0, D == 3 ? (any ? T.ext[2] : 0) : 1, 0);
+}
+
 template <int D>
 __device__ __forceinline__ int tile_global_index(const Tile<D>& T, int q, int n) {
-  int l[D];
+  int c[D];
   int r = q;
 #pragma unroll
-  for (int a = D - 1; a >= 0; --a) {
-    l[a] = r % T.ext[a];
-    r /= T.ext[a];
+  for (int a = D - 1; a > 0; --a) {
+    int m;
+    r = div_small(r, T.ext[a], T.rcp[a], m);
+    c[a] = T.lo[a] + m;
   }
+  c[0] = T.lo[0] + r;
   int g = 0;
 #pragma unroll
-  for (int a = 0; a < D; ++a) g = g * n + T.lo[a] + l[a];
+  for (int a = 0; a < D; ++a) g = g * n + c[a];
   return g;
 }
 
@@ -504,10 +592,12 @@ template <int D>
 __device__ __forceinline__ int tile_node(const Tile<D>& T, int q, int n, int (&c)[D]) {
   int r = q;
 #pragma unroll
-  for (int a = D - 1; a >= 0; --a) {
-    c[a] = T.lo[a] + r % T.ext[a];
-    r /= T.ext[a];
+  for (int a = D - 1; a > 0; --a) {
+    int m;
+    r = div_small(r, T.ext[a], T.rcp[a], m);
+    c[a] = T.lo[a] + m;
   }
+  c[0] = T.lo[0] + r;
   int g = 0;
 #pragma unroll
   for (int a = 0; a < D; ++a) g = g * n + c[a];
@@ -880,7 +970,7 @@ __device__ __forceinline__ int actuator_of(const StepConsts& k, const float* act
 template <int D, int LPP>
 __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i, int sc, bool one_scene, int sub,
                                           int count, const PState<D>& p, const float* act_row, float4* grid,
-                                          long long* tile, int* red, unsigned& err) {
+                                          long long* tile, int* red, unsigned& err, int4* box_out, int wg) {
   constexpr int S0 = (LPP == 4) ? 1 : 3;
   Sten<D> st;
   const bool fin = live && state_finite<D>(p);
@@ -900,6 +990,7 @@ __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i,
     bound = p2g_bound<D>(mass, mv, A, k.dx);
   }
   Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
+  record_box<D>(box_out, wg, T, one_scene ? sc : -1);
   if (T.on) {
     T.e = block_scale(bound, count, red);
     T.on = T.e != INT_MIN;
@@ -969,7 +1060,10 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   __shared__ long long tile64[4 * kTileMax];
   __shared__ int red[8];
   float* tile = reinterpret_cast<float*>(tile64);
-  zero_range(a.clear, a.clear_n);
+  if (a.clear_box)
+    clear_boxes<D>(a.clear, a.clear_box, a.clear_nbox, nullptr, nullptr, 0, a.k.n, a.k.nodes, a.k.n_scenes);
+  else
+    zero_range(a.clear, a.clear_n);
   const StepConsts& k = a.k;
   const LaneMap<LPP> lm(k, int(blockIdx.x));
   const int first = lm.first, i = lm.i, sub = lm.sub;
@@ -1001,7 +1095,9 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
     }
     if (live && lm.owner) store_state<D>(a.out, i, p);
   }
-  if (a.do_p2g) p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_row, a.grid_out, tile64, red, err);
+  if (a.do_p2g)
+    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_row, a.grid_out, tile64, red, err, a.box_out,
+                      int(blockIdx.x));
   if (err) atomicOr(k.err, err);
 }
 
@@ -1027,14 +1123,18 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   __shared__ long long tileB64[4 * kTileMax];
   __shared__ int red[8];
   float* tileA = reinterpret_cast<float*>(tileA64);
-  zero_range(a.clear0, a.clear0_n);
-  zero_range(a.clear1, a.clear1_n);
+  if (a.clear0_box || a.clear1_box)
+    clear_boxes<D>(a.clear0, a.clear0_box, a.clear0_nbox, a.clear1, a.clear1_box, a.clear1_nbox, a.k.n, a.k.nodes,
+                   a.k.n_scenes);
+  if (!a.clear0_box) zero_range(a.clear0, a.clear0_n);
+  if (!a.clear1_box) zero_range(a.clear1, a.clear1_n);
   const StepConsts& k = a.k;
   // With split_c, workgroups [0, nb) run phases A and B and workgroups
   // [nb, 2 nb) run phase C on the same particles: C does not depend on A or B.
   const int nb = k.n_blocks;
   const bool role_c = a.split_c && int(blockIdx.x) >= nb;
-  const LaneMap<LPP> lm(k, role_c ? int(blockIdx.x) - nb : int(blockIdx.x));
+  const int wg = role_c ? int(blockIdx.x) - nb : int(blockIdx.x);
+  const LaneMap<LPP> lm(k, wg);
   const int first = lm.first, i = lm.i, sub = lm.sub;
   const bool live = lm.live, owner = lm.owner;
   // Threads past the end take the scene of the workgroup's first particle:
@@ -1045,7 +1145,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   if (role_c) {
     PState<D> p;
     if (live) load_state<D>(a.stC, i, p);
-    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_rowC, a.gC, tileA64, red, err);
+    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_rowC, a.gC, tileA64, red, err, a.boxC, wg);
     if (err) atomicOr(k.err, err);
     return;
   }
@@ -1185,6 +1285,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     for (int c = 0; c < D; ++c) fin = fin && (p.x[c] * 0.0f == 0.0f);
     const bool ok = fin && lane_sten<D, LPP>(k, p.x, sub, st);
     Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
+    record_box<D>(a.boxB, wg, T, one_scene ? sc : -1);
     const float4* g = a.gB + long(sc) * k.nodes;
     float4* ad = a.aB + long(sc) * k.nodes;
     if (T.on) {
@@ -1262,7 +1363,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   if (a.do_c && !a.split_c) {
     PState<D> p;
     if (live) load_state<D>(a.stC, i, p);
-    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_rowC, a.gC, tileA64, red, err);
+    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_rowC, a.gC, tileA64, red, err, a.boxC, wg);
   }
   if (err) atomicOr(k.err, err);
 }

@@ -184,10 +184,11 @@ __global__ void k_gather_i32(const int* src, int* dst, const int* perm, int N) {
   dst[i] = src[perm ? perm[i] : i];
 }
 
-// One workgroup per scene: L_k = sign * mean_p x_{p,axis}; the seed gets
-// sign / N_k on the loss axis of x and zero in every other component.
+// One workgroup per scene: L_k = sign * mean_p x_{p,axis} (FP64 sum in a
+// fixed order).
 template <int D>
-__global__ void k_loss_mean(StateRef fin, const int* offsets, int axis, float sign, float* loss, StateRef seed) {
+__global__ void __launch_bounds__(1024) k_loss_mean(StateRef fin, const int* offsets, int axis, float sign,
+                                                    float* loss) {
   __shared__ double sh[1024 / 64];
   const int sc = blockIdx.x;
   const int lo = offsets[sc], hi = offsets[sc + 1];
@@ -202,20 +203,32 @@ __global__ void k_loss_mean(StateRef fin, const int* offsets, int axis, float si
     for (int q = 0; q < nw; ++q) t += sh[q];
     loss[sc] = (hi > lo) ? float(double(sign) * t / double(hi - lo)) : 0.0f;
   }
-  if (seed.x) {
-    const float g = (hi > lo) ? sign / float(hi - lo) : 0.0f;
-    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+}
+
+// dL/dstate of the mean-position loss, one thread per particle: sign / N_k on
+// the loss axis of x (k = the particle's scene), zero in every other component.
+template <int D>
+__global__ void k_loss_seed(const int* offsets, int n_scenes, int N, int axis, float sign, StateRef seed) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int a = 0, b = n_scenes;  // offsets[a] <= i < offsets[b]
+  while (b - a > 1) {
+    const int m = (a + b) >> 1;
+    if (offsets[m] <= i)
+      a = m;
+    else
+      b = m;
+  }
+  const float g = sign / float(offsets[a + 1] - offsets[a]);
 #pragma unroll
-      for (int c = 0; c < D; ++c) {
-        seed.x[c * seed.stride + i] = (c == axis) ? g : 0.0f;
-        seed.v[c * seed.stride + i] = 0.0f;
-      }
+  for (int c = 0; c < D; ++c) {
+    seed.x[c * seed.stride + i] = (c == axis) ? g : 0.0f;
+    seed.v[c * seed.stride + i] = 0.0f;
+  }
 #pragma unroll
-      for (int c = 0; c < D * D; ++c) {
-        seed.C[c * seed.stride + i] = 0.0f;
-        seed.F[c * seed.stride + i] = 0.0f;
-      }
-    }
+  for (int c = 0; c < D * D; ++c) {
+    seed.C[c * seed.stride + i] = 0.0f;
+    seed.F[c * seed.stride + i] = 0.0f;
   }
 }
 

@@ -89,3 +89,23 @@ def test_autotune_picks_and_caches(tmp_path):
     assert again == best
     g = rt.Simulator.for_scene(sc, knobs=best)
     assert g.N == sc.n_particles
+
+
+def test_launch_shape_change_between_trajectories():
+    """One context, the launch shape changed between trajectories (the number
+    of workgroups, hence the per-workgroup scatter boxes the reverse pass
+    clears, changes): same trajectory and gradients as a fresh context."""
+    sc = scenes.c1d().with_steps(24)
+    w = random_seed(sc, 5)
+    p = rt.params_for_scene(sc)
+    init = rt.state_for_scene(sc)
+    sim = rt.Simulator.for_scene(sc, knobs={"block": 256})
+    first = _run(sim, sc, sim.tape(24, 4), p, init, w)[0]
+    sim.set_knob("block", 64)
+    second = _run(sim, sc, sim.tape(24, 4), p, init, w)[0]
+    fresh_sim = rt.Simulator.for_scene(sc, knobs={"block": 64})
+    fresh = _run(fresh_sim, sc, fresh_sim.tape(24, 4), p, init, w)[0]
+    assert rel(second[0], fresh[0]) < 1e-6
+    assert min(cos(second[1][k], fresh[1][k]) for k in range(4)) > 0.99999
+    assert rel(first[0], fresh[0]) < 1e-4
+    assert sim.check_errors() == 0
