@@ -240,6 +240,12 @@ int4* scatter_into(const mpm_ctx& c, int g) {
   return nullptr;
 }
 
+// Box table of grid g when its content came from one scatter launch of the
+// current launch shape (the gather of g can reuse the boxes), else null.
+const int4* recorded_boxes(const mpm_ctx& c, int g) {
+  return (c.lds && c.gstate[g] == c.n_blocks) ? box_table(c, g) : nullptr;
+}
+
 // Clear of grid g by a step launch: nothing (already zero), its recorded
 // boxes, or the whole grid.
 void plan_clear(const mpm_ctx& c, int g, float4*& ptr, long& n, const int4*& box, int& nbox) {
@@ -429,6 +435,7 @@ mpm_status run_forward(mpm_tape& tp, const mpm_params* p, int t0, int t1, hipStr
     b.in = tp.slot(t);
     b.out = tp.slot(t + 1);
     b.grid_in = c.grid(kGridF + u % 3);
+    b.box_in = recorded_boxes(c, kGridF + u % 3);
     b.do_g2p = 1;
     b.do_p2g = (t + 1 < t1) ? 1 : 0;
     b.grid_out = c.grid(kGridF + (u + 1) % 3);
@@ -854,6 +861,7 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
       b.stA = tape->slot(st + 1);
       b.gA = gB(st + 1);
       b.aA = aB(st + 1);
+      b.boxA_in = recorded_boxes(c, iB(st + 1));
       b.act_rowA = act_row(c, params, st + 1);
       b.gact_rowA = (c.n_act > 0) ? tape->gact() + size_t(st + 1) * c.n_act : nullptr;
       b.gE = c.at<double>(R_GE);
@@ -864,6 +872,7 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
     b.cnext_stride = nx.stride;
     b.gB = gB(st);
     b.aB = aB(st);
+    b.boxB_in = recorded_boxes(c, iB(st));
     // Grid st+2 and adjoint grid st+2 were last read by the previous launch
     // (phase A); neither is touched by this one.
     plan_clear(c, iB(st + 2), b.clear0, b.clear0_n, b.clear0_box, b.clear0_nbox);
@@ -885,6 +894,7 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
     b.stA = tape->slot(0);
     b.gA = gB(0);
     b.aA = aB(0);
+    b.boxA_in = recorded_boxes(c, iB(0));
     b.act_rowA = act_row(c, params, 0);
     b.gact_rowA = (c.n_act > 0) ? tape->gact() : nullptr;
     b.gE = c.at<double>(R_GE);

@@ -77,6 +77,7 @@ struct FwdArgs {
   const int4* clear_box;   // or: the boxes its last scatter recorded (clear_nbox workgroups)
   int clear_nbox;
   int4* box_out;           // box table of grid_out (record_box), or null
+  const int4* box_in;      // box table the scatter into grid_in recorded (this launch's workgroups), or null
 };
 
 struct BwdArgs {
@@ -120,6 +121,8 @@ struct BwdArgs {
   int clear1_nbox;
   int4* boxB;              // box tables of aB and gC (record_box), or null
   int4* boxC;
+  const int4* boxA_in;     // box tables the scatters into gA and gB recorded, or null
+  const int4* boxB_in;
 };
 
 // Visits the stencil nodes (t0, t1, t2); S0 = 3 visits all, S0 = 1 only the
@@ -237,18 +240,66 @@ __device__ __forceinline__ void clear_box_nodes(float4* grid, int4 lo, int4 ex, 
   }
 }
 
-// Clears the boxes of two tables (either may be null), entries distributed
-// over the launch's workgroups.
-template <int D>
-__device__ __forceinline__ void clear_boxes(float4* g0, const int4* t0, int n0, float4* g1, const int4* t1, int n1,
-                                            int n, int nodes, int n_scenes) {
-  const int m0 = t0 ? n0 : 0, m1 = t1 ? n1 : 0;
-  for (int j = blockIdx.x; j < m0 + m1; j += gridDim.x) {
-    const bool first = j < m0;
-    const int4* t = first ? t0 : t1;
-    const int jj = first ? j : j - m0;
-    clear_box_nodes<D>(first ? g0 : g1, t[2 * jj], t[2 * jj + 1], n, nodes, n_scenes);
+// One grid a launch clears: by its recorded boxes (box, nbox entries) or
+// densely (dense_n float4), or not at all (g null).
+struct ClearSpec {
+  float4* g;
+  const int4* box;
+  int nbox;
+  long dense_n;
+};
+
+// The box entries of two concatenated tables are spread over the launch's
+// workgroups; a workgroup fetches its first two entries early (the loads
+// overlap its other reads) and clears them later.
+struct ClearJobs {
+  int4 lo[2], ex[2];
+  int which[2];
+  int n;
+};
+
+__device__ __forceinline__ int clear_entries(const ClearSpec& s) { return (s.g && s.box) ? s.nbox : 0; }
+
+__device__ __forceinline__ void clear_entry(const ClearSpec& s0, const ClearSpec& s1, int j, int4& lo, int4& ex,
+                                            int& which) {
+  const int m0 = clear_entries(s0);
+  which = j < m0 ? 0 : 1;
+  const int4* t = which == 0 ? s0.box : s1.box;
+  const int jj = which == 0 ? j : j - m0;
+  lo = t[2 * jj];
+  ex = t[2 * jj + 1];
+}
+
+__device__ __forceinline__ ClearJobs clear_jobs_fetch(const ClearSpec& s0, const ClearSpec& s1) {
+  ClearJobs c;
+  c.n = 0;
+  const int m = clear_entries(s0) + clear_entries(s1);
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int j = int(blockIdx.x) + r * int(gridDim.x);
+    if (j < m) {
+      clear_entry(s0, s1, j, c.lo[r], c.ex[r], c.which[r]);
+      c.n = r + 1;
+    }
   }
+  return c;
+}
+
+template <int D>
+__device__ __forceinline__ void clear_jobs_run(const ClearJobs& c, const ClearSpec& s0, const ClearSpec& s1, int n,
+                                               int nodes, int n_scenes) {
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+    if (r < c.n) clear_box_nodes<D>(c.which[r] == 0 ? s0.g : s1.g, c.lo[r], c.ex[r], n, nodes, n_scenes);
+  const int m = clear_entries(s0) + clear_entries(s1);
+  for (int j = int(blockIdx.x) + 2 * int(gridDim.x); j < m; j += int(gridDim.x)) {
+    int4 lo, ex;
+    int which;
+    clear_entry(s0, s1, j, lo, ex, which);
+    clear_box_nodes<D>(which == 0 ? s0.g : s1.g, lo, ex, n, nodes, n_scenes);
+  }
+  if (s0.g && !s0.box) zero_range(s0.g, s0.dense_n);
+  if (s1.g && !s1.box) zero_range(s1.g, s1.dense_n);
 }
 
 __device__ __forceinline__ void atomic_add_f32(float* p, float v) { unsafeAtomicAdd(p, v); }
@@ -472,7 +523,6 @@ __device__ __forceinline__ bool block_one_scene(const StepConsts& k, int first, 
   return k.scene_id[first] == k.scene_id[last];
 }
 
-// Block-wide box of the stencil bases of the valid lanes (all threads call).
 // Fixed-point exponent for `count` contributions bounded by `bmax`: the
 // largest e with count * bmax < 2^(62 - e); INT_MIN when the bound is not finite.
 __device__ __forceinline__ int fixed_exponent(float bmax, int count) {
@@ -482,23 +532,75 @@ __device__ __forceinline__ int fixed_exponent(float bmax, int count) {
   return 62 - (ilogbf(total) + 1);
 }
 
-// Block-wide max of a non-negative bound (all threads call); returns the
-// fixed-point exponent for `count` contributions of at most that size.
-__device__ __forceinline__ int block_scale(float bound, int count, int* red) {
-  if (threadIdx.x == 0) red[7] = 0;
-  __syncthreads();
-  int b = __float_as_int(bound > 0.0f ? bound : 0.0f);  // non-negative floats order as ints; NaN is largest
+// Block-wide reductions with one barrier each: every wave writes its partial
+// to its own slots in one of two alternating slot sets (2 x 4 waves x 8 ints),
+// and a set is written again only after a later reduction's barrier, which
+// every thread reaches after reading it.
+struct BlockRed {
+  int* sh;
+  int phase;
+};
+
+template <int D>
+struct Box {
+  int mn[D], mx[D];
+  float bmax;
+};
+
+// Min/max of the stencil bases of the valid lanes and max of `bound` (a
+// non-negative contribution bound; NaN counts as +inf). All threads call.
+template <int D>
+__device__ Box<D> block_reduce(bool valid, const int (&base)[D], float bound, BlockRed& r) {
+  int mn[D], mx[D];
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) b = max(b, __shfl_xor(b, off, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(red + 7, b);
+  for (int a = 0; a < D; ++a) {
+    mn[a] = valid ? base[a] : INT_MAX;
+    mx[a] = valid ? base[a] : INT_MIN;
+  }
+  const float bb = (bound == bound) ? fmaxf(bound, 0.0f) : __int_as_float(0x7f800000);
+  int b = __float_as_int(bb);  // non-negative floats order as ints
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      mn[a] = min(mn[a], __shfl_xor(mn[a], off, 64));
+      mx[a] = max(mx[a], __shfl_xor(mx[a], off, 64));
+    }
+    b = max(b, __shfl_xor(b, off, 64));
+  }
+  int* s = r.sh + (r.phase & 1) * 32;
+  const int w = int(threadIdx.x >> 6), nw = int((blockDim.x + 63) >> 6);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      s[w * 8 + a] = mn[a];
+      s[w * 8 + D + a] = mx[a];
+    }
+    s[w * 8 + 2 * D] = b;
+  }
   __syncthreads();
-  const int e = fixed_exponent(__int_as_float(red[7]), count);
-  __syncthreads();
-  return e;
+  Box<D> out;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    out.mn[a] = INT_MAX;
+    out.mx[a] = INT_MIN;
+  }
+  int bm = 0;
+  for (int q = 0; q < nw; ++q) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      out.mn[a] = min(out.mn[a], s[q * 8 + a]);
+      out.mx[a] = max(out.mx[a], s[q * 8 + D + a]);
+    }
+    bm = max(bm, s[q * 8 + 2 * D]);
+  }
+  out.bmax = __int_as_float(bm);
+  ++r.phase;
+  return out;
 }
 
 template <int D>
-__device__ Tile<D> block_tile(bool valid, const int (&base)[D], bool one_scene, int enabled, int* red) {
+__device__ __forceinline__ Tile<D> empty_tile() {
   Tile<D> T;
   T.on = false;
   T.n = 0;
@@ -509,44 +611,97 @@ __device__ Tile<D> block_tile(bool valid, const int (&base)[D], bool one_scene, 
     T.ext[a] = 0;
     T.rcp[a] = 0.0f;
   }
-  if (!enabled) return T;
-  const int t = threadIdx.x;
-  if (t < 2 * D) red[t] = (t < D) ? INT_MAX : INT_MIN;
-  __syncthreads();
-  int mn[D], mx[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    mn[a] = valid ? base[a] : INT_MAX;
-    mx[a] = valid ? base[a] : INT_MIN;
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      mn[a] = min(mn[a], __shfl_xor(mn[a], off, 64));
-      mx[a] = max(mx[a], __shfl_xor(mx[a], off, 64));
-    }
-  if ((t & 63) == 0) {
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      atomicMin(red + a, mn[a]);
-      atomicMax(red + D + a, mx[a]);
-    }
-  }
-  __syncthreads();
-  const bool any = red[0] <= red[D];
-  int n = any ? 1 : 0;
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    T.lo[a] = any ? red[a] : 0;
-    T.ext[a] = any ? red[D + a] - red[a] + 3 : 0;
-    T.rcp[a] = any ? (1.0f / float(T.ext[a])) * (1.0f + 0x1p-20f) : 0.0f;
-    n *= T.ext[a];
-  }
-  T.n = n;
-  T.on = any && one_scene && n <= kTileMax;
-  __syncthreads();
   return T;
+}
+
+template <int D>
+__device__ __forceinline__ void tile_set_box(Tile<D>& T, const int (&lo)[D], const int (&ext)[D]) {
+  int n = 1;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    T.lo[a] = lo[a];
+    T.ext[a] = ext[a];
+    T.rcp[a] = ext[a] > 0 ? (1.0f / float(ext[a])) * (1.0f + 0x1p-20f) : 0.0f;
+    n *= ext[a];
+  }
+  T.n = ext[0] > 0 ? n : 0;
+}
+
+// Box of the stencils of the workgroup's valid lanes (bases lo .. lo + ext - 3).
+template <int D>
+__device__ __forceinline__ Tile<D> tile_of(const Box<D>& bx, bool one_scene) {
+  Tile<D> T = empty_tile<D>();
+  if (bx.mn[0] > bx.mx[0]) return T;  // no valid lane
+  int lo[D], ext[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    lo[a] = bx.mn[a];
+    ext[a] = bx.mx[a] - bx.mn[a] + 3;
+  }
+  tile_set_box<D>(T, lo, ext);
+  T.on = one_scene && T.n <= kTileMax;
+  return T;
+}
+
+template <int D>
+__device__ __forceinline__ Tile<D> block_tile(bool valid, const int (&base)[D], bool one_scene, int enabled,
+                                              BlockRed& r) {
+  if (!enabled) return empty_tile<D>();
+  return tile_of<D>(block_reduce<D>(valid, base, 0.0f, r), one_scene);
+}
+
+// Box and fixed-point exponent of a scatter tile in one reduction.
+template <int D>
+__device__ __forceinline__ Tile<D> block_tile_scaled(bool valid, const int (&base)[D], float bound, int count,
+                                                     bool one_scene, int enabled, BlockRed& r) {
+  if (!enabled) return empty_tile<D>();
+  const Box<D> bx = block_reduce<D>(valid, base, bound, r);
+  Tile<D> T = tile_of<D>(bx, one_scene);
+  T.e = fixed_exponent(bx.bmax, count);
+  T.on = T.on && T.e != INT_MIN;
+  return T;
+}
+
+// Fixed-point exponent alone (all threads call).
+template <int D>
+__device__ __forceinline__ int block_scale(float bound, int count, BlockRed& r) {
+  int none[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) none[a] = 0;
+  return fixed_exponent(block_reduce<D>(false, none, bound, r).bmax, count);
+}
+
+// The box a gather needs, as recorded by the scatter into the same grid one
+// launch earlier (same workgroup, same particle positions). Used only when it
+// lies inside the grid and belongs to this workgroup's scene.
+template <int D>
+__device__ __forceinline__ Tile<D> recorded_tile(const int4* table, int wg, int sc, bool one_scene, int enabled,
+                                                 int n) {
+  Tile<D> T = empty_tile<D>();
+  if (!enabled) return T;
+  const int4 l4 = table[2 * wg], e4 = table[2 * wg + 1];
+  const int lo3[3] = {l4.x, l4.y, l4.z}, ex3[3] = {e4.x, e4.y, e4.z};
+  int lo[D], ext[D];
+  bool inside = true;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    lo[a] = lo3[a];
+    ext[a] = ex3[a];
+    inside = inside && lo[a] >= 0 && ext[a] >= 3 && ext[a] <= n && lo[a] <= n - ext[a];
+  }
+  if (!inside) return T;
+  tile_set_box<D>(T, lo, ext);
+  T.on = one_scene && l4.w == sc && T.n <= kTileMax;
+  return T;
+}
+
+// True when the stencil (base .. base + 2) lies in the tile's box.
+template <int D>
+__device__ __forceinline__ bool in_tile(const Tile<D>& T, const int (&base)[D]) {
+  bool in = true;
+#pragma unroll
+  for (int a = 0; a < D; ++a) in = in && base[a] >= T.lo[a] && base[a] + 3 <= T.lo[a] + T.ext[a];
+  return in;
 }
 
 // Records the box of a scatter's nodes for workgroup `index` (thread 0).
@@ -556,6 +711,27 @@ __device__ __forceinline__ void record_box(int4* table, int index, const Tile<D>
   const bool any = T.n > 0;
   table[2 * index] = make_int4(T.lo[0], T.lo[1], D == 3 ? T.lo[2] : 0, scene);
   table[2 * index + 1] = make_int4(any ? T.ext[0] : 0, any ? T.ext[1] : 0, D == 3 ? (any ? T.ext[2] : 0) : 1, 0);
+}
+
+// Records the union of a tile's box and the stencil-base box `bx` (empty when
+// bx.mn > bx.mx) for workgroup `index`.
+template <int D>
+__device__ __forceinline__ void record_box_union(int4* table, int index, const Tile<D>& T, const Box<D>& bx,
+                                                 int scene) {
+  if (!table) return;
+  Tile<D> U = T;
+  if (bx.mn[0] <= bx.mx[0]) {
+    int lo[D], ext[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int l = (T.n > 0) ? min(T.lo[a], bx.mn[a]) : bx.mn[a];
+      const int h = (T.n > 0) ? max(T.lo[a] + T.ext[a], bx.mx[a] + 3) : bx.mx[a] + 3;
+      lo[a] = l;
+      ext[a] = h - l;
+    }
+    tile_set_box<D>(U, lo, ext);
+  }
+  record_box<D>(table, index, U, scene);
 }
 
 template <int D>
@@ -966,11 +1142,13 @@ __device__ __forceinline__ int actuator_of(const StepConsts& k, const float* act
   return aid;
 }
 
-// Scatter of one state into `grid` with an optional LDS tile (all threads call).
+// Scatter of one state into `grid` with an optional LDS tile (all threads
+// call). The fixed-point tile must already be zero over its first D + 1
+// components (zero_tile64).
 template <int D, int LPP>
 __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i, int sc, bool one_scene, int sub,
                                           int count, const PState<D>& p, const float* act_row, float4* grid,
-                                          long long* tile, int* red, unsigned& err, int4* box_out, int wg) {
+                                          long long* tile, BlockRed& rd, unsigned& err, int4* box_out, int wg) {
   constexpr int S0 = (LPP == 4) ? 1 : 3;
   Sten<D> st;
   const bool fin = live && state_finite<D>(p);
@@ -989,17 +1167,9 @@ __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i,
     mass = sp.mass;
     bound = p2g_bound<D>(mass, mv, A, k.dx);
   }
-  Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
+  const Tile<D> T = block_tile_scaled<D>(ok, st.base, bound, count, one_scene, k.lds, rd);
   record_box<D>(box_out, wg, T, one_scene ? sc : -1);
-  if (T.on) {
-    T.e = block_scale(bound, count, red);
-    T.on = T.e != INT_MIN;
-  }
   float4* g = grid + long(sc) * k.nodes;
-  if (T.on) {
-    tile_zero64<D, D + 1>(T, tile);
-    __syncthreads();
-  }
   if (ok && (LPP == 1 || sub < 3)) {
     if (T.on)
       p2g_body<D, S0>(k, st, mass, mv, A, fix_nodes<D>(tile, T));
@@ -1010,6 +1180,13 @@ __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i,
     __syncthreads();
     tile_flush64<D, D + 1>(T, tile, g, k.n);
   }
+}
+
+// Zeroes the first NC components of a whole fixed-point tile (no barrier: the
+// next block reduction's barrier orders it before the scatter).
+template <int NC>
+__device__ __forceinline__ void zero_tile64(long long* tile) {
+  for (int q = threadIdx.x; q < NC * kTileMax; q += blockDim.x) tile[q] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1057,13 +1234,10 @@ struct LaneMap {
 template <int D, int LPP>
 __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   constexpr int S0 = (LPP == 4) ? 1 : 3;
-  __shared__ long long tile64[4 * kTileMax];
-  __shared__ int red[8];
-  float* tile = reinterpret_cast<float*>(tile64);
-  if (a.clear_box)
-    clear_boxes<D>(a.clear, a.clear_box, a.clear_nbox, nullptr, nullptr, 0, a.k.n, a.k.nodes, a.k.n_scenes);
-  else
-    zero_range(a.clear, a.clear_n);
+  __shared__ long long tile64[(D + 1) * kTileMax];  // P2G scatter tile (fixed point)
+  __shared__ float vtile[D * kTileMax];              // G2P velocity tile
+  __shared__ int red[64];
+  BlockRed rd{red, 0};
   const StepConsts& k = a.k;
   const LaneMap<LPP> lm(k, int(blockIdx.x));
   const int first = lm.first, i = lm.i, sub = lm.sub;
@@ -1073,30 +1247,43 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   const int sc = k.blocks ? lm.scene : (k.scene_id ? k.scene_id[live ? i : first] : 0);
   const bool one_scene = k.blocks ? true : block_one_scene(k, first, lm.count);
   unsigned err = 0;
+  if (a.do_p2g && k.lds) zero_tile64<D + 1>(tile64);
+  const ClearSpec c0{a.clear, a.clear_box, a.clear_nbox, a.clear_n}, c1{nullptr, nullptr, 0, 0};
+  const ClearJobs cj = clear_jobs_fetch(c0, c1);
+  // G2P box: recorded by the scatter into grid_in (the previous launch), so
+  // the tile load needs neither this launch's positions nor a reduction.
+  Tile<D> T = empty_tile<D>();
+  const float4* g = a.grid_in + long(sc) * k.nodes;
+  if (a.do_g2p && a.box_in) {
+    T = recorded_tile<D>(a.box_in, int(blockIdx.x), sc, one_scene, k.lds, k.n);
+    if (T.on) tile_load_vel<D>(k, T, g, vtile);
+  }
   PState<D> p;
   if (live) load_state<D>(a.in, i, p);
   if (a.do_g2p) {
     Sten<D> st;
     const bool fin = live && state_finite<D>(p);
     const bool ok = fin && lane_sten<D, LPP>(k, p.x, sub, st);
-    const Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
-    const float4* g = a.grid_in + long(sc) * k.nodes;
-    if (T.on) {
-      tile_load_vel<D>(k, T, g, tile);
-      __syncthreads();
+    if (!a.box_in) {
+      T = block_tile<D>(ok, st.base, one_scene, k.lds, rd);
+      if (T.on) tile_load_vel<D>(k, T, g, vtile);
     }
+    if (T.on) __syncthreads();
+    clear_jobs_run<D>(cj, c0, c1, k.n, k.nodes, k.n_scenes);
     if (ok) {
-      if (T.on)
-        g2p_body<D, true, S0>(k, st, lds_nodes<D>(tile, T), p);
+      if (T.on && in_tile<D>(T, st.base))
+        g2p_body<D, true, S0>(k, st, lds_nodes<D>(vtile, T), p);
       else
         g2p_body<D, false, S0>(k, st, global_nodes<D>(g, k.n), p);
     } else if (live) {
       err |= fin ? kErrDomain : kErrNonfinite;
     }
     if (live && lm.owner) store_state<D>(a.out, i, p);
+  } else {
+    clear_jobs_run<D>(cj, c0, c1, k.n, k.nodes, k.n_scenes);
   }
   if (a.do_p2g)
-    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_row, a.grid_out, tile64, red, err, a.box_out,
+    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_row, a.grid_out, tile64, rd, err, a.box_out,
                       int(blockIdx.x));
   if (err) atomicOr(k.err, err);
 }
@@ -1119,15 +1306,11 @@ __device__ __forceinline__ void wave_add_keyed(bool live, int key, double val, d
 template <int D, int LPP>
 __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   constexpr int S0 = (LPP == 4) ? 1 : 3;
-  __shared__ long long tileA64[4 * kTileMax];
-  __shared__ long long tileB64[4 * kTileMax];
-  __shared__ int red[8];
-  float* tileA = reinterpret_cast<float*>(tileA64);
-  if (a.clear0_box || a.clear1_box)
-    clear_boxes<D>(a.clear0, a.clear0_box, a.clear0_nbox, a.clear1, a.clear1_box, a.clear1_nbox, a.k.n, a.k.nodes,
-                   a.k.n_scenes);
-  if (!a.clear0_box) zero_range(a.clear0, a.clear0_n);
-  if (!a.clear1_box) zero_range(a.clear1, a.clear1_n);
+  __shared__ float tA[(D + 1) * kTileMax];      // phase A: adjoint tile (P*, m*)
+  __shared__ float tV[D * kTileMax];            // phase B: velocity tile
+  __shared__ long long tS[(D + 1) * kTileMax];  // scatter tile: phase B (adjoint grid), phase C (grid)
+  __shared__ int red[64];
+  BlockRed rd{red, 0};
   const StepConsts& k = a.k;
   // With split_c, workgroups [0, nb) run phases A and B and workgroups
   // [nb, 2 nb) run phase C on the same particles: C does not depend on A or B.
@@ -1142,12 +1325,29 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   const int sc = k.blocks ? lm.scene : (k.scene_id ? k.scene_id[live ? i : first] : 0);
   const bool one_scene = k.blocks ? true : block_one_scene(k, first, lm.count);
   unsigned err = 0;
+  const ClearSpec c0{a.clear0, a.clear0_box, a.clear0_nbox, a.clear0_n};
+  const ClearSpec c1{a.clear1, a.clear1_box, a.clear1_nbox, a.clear1_n};
+  const ClearJobs cj = clear_jobs_fetch(c0, c1);
   if (role_c) {
+    if (k.lds) zero_tile64<D + 1>(tS);
     PState<D> p;
     if (live) load_state<D>(a.stC, i, p);
-    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_rowC, a.gC, tileA64, red, err, a.boxC, wg);
+    clear_jobs_run<D>(cj, c0, c1, k.n, k.nodes, k.n_scenes);
+    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
     if (err) atomicOr(k.err, err);
     return;
+  }
+  if (!a.final_out && k.lds) zero_tile64<D>(tS);
+  // Gather boxes recorded by the scatters into grid s+1 (phase A) and grid s
+  // (phase B): both tile loads start before this launch's state arrives.
+  Tile<D> TA = empty_tile<D>(), TB = empty_tile<D>();
+  if (a.a_mode == 1 && a.boxA_in) {
+    TA = recorded_tile<D>(a.boxA_in, wg, sc, one_scene, k.lds, k.n);
+    if (TA.on) tile_load_adj<D>(k, TA, a.gA + long(sc) * k.nodes, a.aA + long(sc) * k.nodes, tA);
+  }
+  if (!a.final_out && a.boxB_in) {
+    TB = recorded_tile<D>(a.boxB_in, wg, sc, one_scene, k.lds, k.n);
+    if (TB.on) tile_load_vel<D>(k, TB, a.gB + long(sc) * k.nodes, tV);
   }
 
   // dL/dstate(s+1): gx, gv, gC, gF.
@@ -1183,11 +1383,11 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     }
     Sten<D> st;
     const bool ok = live && state_finite<D>(p) && lane_sten<D, LPP>(k, p.x, sub, st);
-    const Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
     const float4* g = a.gA + long(sc) * k.nodes;
     const float4* ad = a.aA + long(sc) * k.nodes;
+    const Tile<D> T = a.boxA_in ? TA : block_tile<D>(ok, st.base, one_scene, k.lds, rd);
     if (T.on) {
-      tile_load_adj<D>(k, T, g, ad, tileA);
+      if (!a.boxA_in) tile_load_adj<D>(k, T, g, ad, tA);
       __syncthreads();
     }
     if (ok) {
@@ -1201,9 +1401,8 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
 #pragma unroll
       for (int c = 0; c < D; ++c) mv[c] = sp.mass * p.v[c];
       float Abar[D][D] = {}, vb[D] = {};
-      if (T.on)
-        p2g_adj_body<D, true, S0>(k, st, sp.mass, mv, A, lds_nodes<D>(tileA, T), lds_nodes<D>(tileA, T), gx, vb,
-                                  Abar);
+      if (T.on && in_tile<D>(T, st.base))
+        p2g_adj_body<D, true, S0>(k, st, sp.mass, mv, A, lds_nodes<D>(tA, T), lds_nodes<D>(tA, T), gx, vb, Abar);
       else
         p2g_adj_body<D, false, S0>(k, st, sp.mass, mv, A, global_nodes<D>(g, k.n), global_nodes<D>(ad, k.n), gx, vb,
                                    Abar);
@@ -1250,6 +1449,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   }
 
   if (a.final_out) {
+    clear_jobs_run<D>(cj, c0, c1, k.n, k.nodes, k.n_scenes);
     if (!live || !owner) return;
     const int o = a.out_perm ? a.out_perm[i] : i;
     const int os = a.out.stride;
@@ -1284,15 +1484,16 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
 #pragma unroll
     for (int c = 0; c < D; ++c) fin = fin && (p.x[c] * 0.0f == 0.0f);
     const bool ok = fin && lane_sten<D, LPP>(k, p.x, sub, st);
-    Tile<D> T = block_tile<D>(ok, st.base, one_scene, k.lds, red);
-    record_box<D>(a.boxB, wg, T, one_scene ? sc : -1);
     const float4* g = a.gB + long(sc) * k.nodes;
     float4* ad = a.aB + long(sc) * k.nodes;
-    if (T.on) {
-      tile_load_vel<D>(k, T, g, tileA);
-      tile_zero64<D, D>(T, tileB64);
-      __syncthreads();
+    Tile<D> T = TB;
+    if (!a.boxB_in) {
+      T = block_tile<D>(ok, st.base, one_scene, k.lds, rd);
+      if (T.on) tile_load_vel<D>(k, T, g, tV);
     }
+    if (T.on) __syncthreads();
+    clear_jobs_run<D>(cj, c0, c1, k.n, k.nodes, k.n_scenes);
+    const bool in_t = T.on && ok && in_tile<D>(T, st.base);
     float Bm[D][D] = {}, vt[D] = {}, bound = 0.0f;
     if (ok) {
       float Cn[D][D];
@@ -1301,8 +1502,8 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
         for (int c = 0; c < D; ++c)
 #pragma unroll
           for (int b = 0; b < D; ++b) Cn[c][b] = a.cnext[(c * D + b) * a.cnext_stride + i];
-      } else if (T.on) {
-        g2p_C<D, true, S0>(k, st, lds_nodes<D>(tileA, T), Cn);
+      } else if (in_t) {
+        g2p_C<D, true, S0>(k, st, lds_nodes<D>(tV, T), Cn);
       } else {
         g2p_C<D, false, S0>(k, st, global_nodes<D>(g, k.n), Cn);
       }
@@ -1330,24 +1531,40 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
         bound = fmaxf(bound, b);
       }
     }
-    // The scatter tile's scale needs the bound of every particle of the workgroup.
-    bool fix = T.on;
-    if (T.on) {
-      T.e = block_scale(bound, lm.count, red);
-      fix = T.e != INT_MIN;
+    // One reduction: the scatter scale (bound of every particle of the
+    // workgroup) and the box of the particles the tile does not cover (none
+    // unless a recorded box missed one), so the recorded scatter box covers all.
+    int e_fix = INT_MIN;
+    Box<D> outside;
+    if (k.lds) {
+      outside = block_reduce<D>(ok && !in_t, st.base, bound, rd);
+      e_fix = fixed_exponent(outside.bmax, lm.count);
+    } else {
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        outside.mn[c] = INT_MAX;
+        outside.mx[c] = INT_MIN;
+      }
     }
+    record_box_union<D>(a.boxB, wg, T, outside, one_scene ? sc : -1);
+    const bool fix = T.on && e_fix != INT_MIN;
     if (ok) {
       const bool scatter = LPP == 1 || sub < 3;
-      if (T.on && fix)
-        g2p_adj_body<D, S0>(k, st, vt, Bm, lds_nodes<D>(tileA, T), fix_nodes<D>(tileB64, T), px, scatter);
-      else if (T.on)
-        g2p_adj_body<D, S0>(k, st, vt, Bm, lds_nodes<D>(tileA, T), global_nodes<D>(ad, k.n), px, scatter);
-      else
+      if (in_t && fix) {
+        FixNodes<D> fn = fix_nodes<D>(tS, T);
+        fn.e = e_fix;
+        g2p_adj_body<D, S0>(k, st, vt, Bm, lds_nodes<D>(tV, T), fn, px, scatter);
+      } else if (in_t) {
+        g2p_adj_body<D, S0>(k, st, vt, Bm, lds_nodes<D>(tV, T), global_nodes<D>(ad, k.n), px, scatter);
+      } else {
         g2p_adj_body<D, S0>(k, st, vt, Bm, global_nodes<D>(g, k.n), global_nodes<D>(ad, k.n), px, scatter);
+      }
     }
-    if (T.on && fix) {
+    if (fix) {
+      Tile<D> TS = T;
+      TS.e = e_fix;
       __syncthreads();
-      tile_flush64<D, D>(T, tileB64, ad, k.n);
+      tile_flush64<D, D>(TS, tS, ad, k.n);
     }
     if (live && owner) {
 #pragma unroll
@@ -1363,7 +1580,9 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   if (a.do_c && !a.split_c) {
     PState<D> p;
     if (live) load_state<D>(a.stC, i, p);
-    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_rowC, a.gC, tileA64, red, err, a.boxC, wg);
+    __syncthreads();  // every thread is done with the scatter tile of phase B
+    if (k.lds) zero_tile64<D + 1>(tS);
+    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
   }
   if (err) atomicOr(k.err, err);
 }
