@@ -186,7 +186,6 @@ StepConsts consts(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
   k.lds = c.lds;
   k.remap = c.remap;
   k.rotate = c.rotate;
-  k.scene_id = c.ns > 1 ? c.at<int>(R_SCENE_ID) : nullptr;
   k.blocks = c.ns > 1 ? c.at<int4>(R_BLOCKS) : nullptr;
   k.n_blocks = c.n_blocks;
   k.E = p->E;

@@ -53,8 +53,8 @@ struct StepConsts {
   int remap;      // 1: interleave the workgroup's particles across waves (lane_particle)
   int rotate;     // 1: per-lane stencil visiting order (Sten, lane_color)
   float dx, inv_dx, dt, gdt, kappa, act_strength;
-  const int* scene_id;  // [N] scene of each particle, or null (one scene)
-  const int4* blocks;   // [n_blocks] scene-aligned workgroups (first, count, scene), or null
+  const int4* blocks;   // [n_blocks] scene-aligned workgroups (first, count, scene); required with
+                        // several scenes, null with one
   int n_blocks;         // workgroups per particle pass
   const float* E;
   const float* nu;
@@ -514,13 +514,6 @@ __device__ __forceinline__ int lane_particle(int t, int B, int remap) {
   if (!remap || (B & 7)) return t;
   const int rows = B >> 3;
   return (t % rows) * 8 + t / rows;
-}
-
-// True when the `count` particles of the workgroup starting at `first` belong to one scene.
-__device__ __forceinline__ bool block_one_scene(const StepConsts& k, int first, int count) {
-  if (!k.scene_id) return true;
-  const int last = min(first + count, k.N) - 1;
-  return k.scene_id[first] == k.scene_id[last];
 }
 
 // Fixed-point exponent for `count` contributions bounded by `bmax`: the
@@ -997,17 +990,35 @@ __device__ __forceinline__ void node_adj(const StepConsts& k, const Sten<D>& st,
   }
 }
 
+// Tile loads issue up to kTileBatch node loads per thread before using any,
+// so their latencies overlap (a box of up to kTileMax nodes takes one round
+// trip at 128 or more threads per workgroup).
+constexpr int kTileBatch = 4;
+
 // Velocity tile: grid_op applied once per node of the box as it is staged
 // (components 0..D-1 = v), so gathers read v instead of forming P / m per visit.
 template <int D>
 __device__ __forceinline__ void tile_load_vel(const StepConsts& k, const Tile<D>& T, const float4* g, float* tile) {
-  for (int q = threadIdx.x; q < T.n; q += blockDim.x) {
-    int c[D];
-    const float4 gm = g[tile_node<D>(T, q, k.n, c)];
-    float v[D];
-    grid_vel<D>(tile_node_interior<D>(c, k.n, k.bound) && gm.x > 0.0f, gm, k.gdt, v);
+  for (int q0 = threadIdx.x; q0 < T.n; q0 += kTileBatch * blockDim.x) {
+    float4 gm[kTileBatch];
 #pragma unroll
-    for (int a = 0; a < D; ++a) tile[a * kTileMax + q] = v[a];
+    for (int r = 0; r < kTileBatch; ++r) {
+      const int q = q0 + r * int(blockDim.x);
+      int c[D];
+      if (q < T.n) gm[r] = g[tile_node<D>(T, q, k.n, c)];
+    }
+#pragma unroll
+    for (int r = 0; r < kTileBatch; ++r) {
+      const int q = q0 + r * int(blockDim.x);
+      if (q < T.n) {
+        int c[D];
+        tile_node<D>(T, q, k.n, c);
+        float v[D];
+        grid_vel<D>(tile_node_interior<D>(c, k.n, k.bound) && gm[r].x > 0.0f, gm[r], k.gdt, v);
+#pragma unroll
+        for (int a = 0; a < D; ++a) tile[a * kTileMax + q] = v[a];
+      }
+    }
   }
 }
 
@@ -1016,16 +1027,31 @@ __device__ __forceinline__ void tile_load_vel(const StepConsts& k, const Tile<D>
 template <int D>
 __device__ __forceinline__ void tile_load_adj(const StepConsts& k, const Tile<D>& T, const float4* g,
                                               const float4* ad, float* tile) {
-  for (int q = threadIdx.x; q < T.n; q += blockDim.x) {
-    int c[D];
-    const int gi = tile_node<D>(T, q, k.n, c);
-    const float4 gm = g[gi];
-    const float4 vb4 = ad[gi];
-    float Pb[D], mb;
-    grid_adj<D>(tile_node_interior<D>(c, k.n, k.bound) && gm.x > 0.0f, gm, vb4, Pb, mb);
+  for (int q0 = threadIdx.x; q0 < T.n; q0 += kTileBatch * blockDim.x) {
+    float4 gm[kTileBatch], vb4[kTileBatch];
 #pragma unroll
-    for (int a = 0; a < D; ++a) tile[a * kTileMax + q] = Pb[a];
-    tile[D * kTileMax + q] = mb;
+    for (int r = 0; r < kTileBatch; ++r) {
+      const int q = q0 + r * int(blockDim.x);
+      int c[D];
+      if (q < T.n) {
+        const int gi = tile_node<D>(T, q, k.n, c);
+        gm[r] = g[gi];
+        vb4[r] = ad[gi];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kTileBatch; ++r) {
+      const int q = q0 + r * int(blockDim.x);
+      if (q < T.n) {
+        int c[D];
+        tile_node<D>(T, q, k.n, c);
+        float Pb[D], mb;
+        grid_adj<D>(tile_node_interior<D>(c, k.n, k.bound) && gm[r].x > 0.0f, gm[r], vb4[r], Pb, mb);
+#pragma unroll
+        for (int a = 0; a < D; ++a) tile[a * kTileMax + q] = Pb[a];
+        tile[D * kTileMax + q] = mb;
+      }
+    }
   }
 }
 
@@ -1240,26 +1266,27 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   BlockRed rd{red, 0};
   const StepConsts& k = a.k;
   const LaneMap<LPP> lm(k, int(blockIdx.x));
-  const int first = lm.first, i = lm.i, sub = lm.sub;
+  const int i = lm.i, sub = lm.sub;
   const bool live = lm.live;
-  // Threads past the end take the scene of the workgroup's first particle:
-  // they still load and flush the workgroup's LDS tile.
-  const int sc = k.blocks ? lm.scene : (k.scene_id ? k.scene_id[live ? i : first] : 0);
-  const bool one_scene = k.blocks ? true : block_one_scene(k, first, lm.count);
+  // Every workgroup holds particles of one scene (scene-aligned workgroups).
+  const int sc = lm.scene;
+  const bool one_scene = true;
   unsigned err = 0;
-  if (a.do_p2g && k.lds) zero_tile64<D + 1>(tile64);
+  // Every independent global read is issued first: the state, the clear
+  // boxes, and the G2P box recorded by the scatter into grid_in (the previous
+  // launch), so the tile load needs neither this launch's positions nor a
+  // reduction and its latency overlaps the state's.
+  PState<D> p;
+  if (live) load_state<D>(a.in, i, p);
   const ClearSpec c0{a.clear, a.clear_box, a.clear_nbox, a.clear_n}, c1{nullptr, nullptr, 0, 0};
   const ClearJobs cj = clear_jobs_fetch(c0, c1);
-  // G2P box: recorded by the scatter into grid_in (the previous launch), so
-  // the tile load needs neither this launch's positions nor a reduction.
+  if (a.do_p2g && k.lds) zero_tile64<D + 1>(tile64);
   Tile<D> T = empty_tile<D>();
   const float4* g = a.grid_in + long(sc) * k.nodes;
   if (a.do_g2p && a.box_in) {
     T = recorded_tile<D>(a.box_in, int(blockIdx.x), sc, one_scene, k.lds, k.n);
     if (T.on) tile_load_vel<D>(k, T, g, vtile);
   }
-  PState<D> p;
-  if (live) load_state<D>(a.in, i, p);
   if (a.do_g2p) {
     Sten<D> st;
     const bool fin = live && state_finite<D>(p);
@@ -1318,12 +1345,11 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   const bool role_c = a.split_c && int(blockIdx.x) >= nb;
   const int wg = role_c ? int(blockIdx.x) - nb : int(blockIdx.x);
   const LaneMap<LPP> lm(k, wg);
-  const int first = lm.first, i = lm.i, sub = lm.sub;
+  const int i = lm.i, sub = lm.sub;
   const bool live = lm.live, owner = lm.owner;
-  // Threads past the end take the scene of the workgroup's first particle:
-  // they still load and flush the workgroup's LDS tile.
-  const int sc = k.blocks ? lm.scene : (k.scene_id ? k.scene_id[live ? i : first] : 0);
-  const bool one_scene = k.blocks ? true : block_one_scene(k, first, lm.count);
+  // Every workgroup holds particles of one scene (scene-aligned workgroups).
+  const int sc = lm.scene;
+  const bool one_scene = true;
   unsigned err = 0;
   const ClearSpec c0{a.clear0, a.clear0_box, a.clear0_nbox, a.clear0_n};
   const ClearSpec c1{a.clear1, a.clear1_box, a.clear1_nbox, a.clear1_n};
@@ -1337,25 +1363,15 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     if (err) atomicOr(k.err, err);
     return;
   }
-  if (!a.final_out && k.lds) zero_tile64<D>(tS);
-  // Gather boxes recorded by the scatters into grid s+1 (phase A) and grid s
-  // (phase B): both tile loads start before this launch's state arrives.
-  Tile<D> TA = empty_tile<D>(), TB = empty_tile<D>();
-  if (a.a_mode == 1 && a.boxA_in) {
-    TA = recorded_tile<D>(a.boxA_in, wg, sc, one_scene, k.lds, k.n);
-    if (TA.on) tile_load_adj<D>(k, TA, a.gA + long(sc) * k.nodes, a.aA + long(sc) * k.nodes, tA);
-  }
-  if (!a.final_out && a.boxB_in) {
-    TB = recorded_tile<D>(a.boxB_in, wg, sc, one_scene, k.lds, k.n);
-    if (TB.on) tile_load_vel<D>(k, TB, a.gB + long(sc) * k.nodes, tV);
-  }
-
-  // dL/dstate(s+1): gx, gv, gC, gF.
+  // Every independent global read is issued first: dL/dstate(s+1) (seed, or
+  // state s+1 and the x*, F* partials), phase B's inputs (x, F of state s and
+  // C of state s+1), then the gather boxes recorded by the scatters into grid
+  // s+1 (phase A) and grid s (phase B) and both tile loads, so no phase waits
+  // for a read it could have started earlier.
   float gx[D] = {}, gv[D] = {}, gC[D][D] = {}, gF[D][D] = {};
-  double eb = 0.0, actb = 0.0;
-  int aid = -1;
-  if (a.a_mode == 0) {
-    if (live) {
+  PState<D> p;  // phase A: state s+1
+  if (live) {
+    if (a.a_mode == 0) {
 #pragma unroll
       for (int c = 0; c < D; ++c) {
         gx[c] = a.seed.x[c * a.seed.stride + i];
@@ -1368,11 +1384,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
           gC[c][b] = a.seed.C[(c * D + b) * a.seed.stride + i];
           gF[c][b] = a.seed.F[(c * D + b) * a.seed.stride + i];
         }
-    }
-  } else {
-    // p2g*(s+1) with grid_op* folded into the gather.
-    PState<D> p;
-    if (live) {
+    } else {
       load_state<D>(a.stA, i, p);
 #pragma unroll
       for (int c = 0; c < D; ++c) gx[c] = a.partial[c * a.pstride + i];
@@ -1381,6 +1393,34 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
 #pragma unroll
         for (int b = 0; b < D; ++b) gF[c][b] = a.partial[(D + c * D + b) * a.pstride + i];
     }
+  }
+  PState<D> pB;  // phase B: x, F of state s
+  float CnB[D][D] = {};
+  if (!a.final_out && live) {
+    load_xF<D>(a.stB, i, pB);
+    if (a.cnext) {
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int b = 0; b < D; ++b) CnB[c][b] = a.cnext[(c * D + b) * a.cnext_stride + i];
+    }
+  }
+  if (!a.final_out && k.lds) zero_tile64<D>(tS);
+  Tile<D> TA = empty_tile<D>(), TB = empty_tile<D>();
+  if (a.a_mode == 1 && a.boxA_in) {
+    TA = recorded_tile<D>(a.boxA_in, wg, sc, one_scene, k.lds, k.n);
+    if (TA.on) tile_load_adj<D>(k, TA, a.gA + long(sc) * k.nodes, a.aA + long(sc) * k.nodes, tA);
+  }
+  if (!a.final_out && a.boxB_in) {
+    TB = recorded_tile<D>(a.boxB_in, wg, sc, one_scene, k.lds, k.n);
+    if (TB.on) tile_load_vel<D>(k, TB, a.gB + long(sc) * k.nodes, tV);
+  }
+
+  // dL/dstate(s+1): gx, gv, gC, gF.
+  double eb = 0.0, actb = 0.0;
+  int aid = -1;
+  if (a.a_mode == 1) {
+    // p2g*(s+1) with grid_op* folded into the gather.
     Sten<D> st;
     const bool ok = live && state_finite<D>(p) && lane_sten<D, LPP>(k, p.x, sub, st);
     const float4* g = a.gA + long(sc) * k.nodes;
@@ -1470,8 +1510,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
 
   // Phase B: g2p*(s).
   {
-    PState<D> p;
-    if (live) load_xF<D>(a.stB, i, p);
+    const PState<D>& p = pB;
     float px[D], pF[D][D];
 #pragma unroll
     for (int c = 0; c < D; ++c) px[c] = gx[c];
@@ -1501,7 +1540,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
 #pragma unroll
         for (int c = 0; c < D; ++c)
 #pragma unroll
-          for (int b = 0; b < D; ++b) Cn[c][b] = a.cnext[(c * D + b) * a.cnext_stride + i];
+          for (int b = 0; b < D; ++b) Cn[c][b] = CnB[c][b];
       } else if (in_t) {
         g2p_C<D, true, S0>(k, st, lds_nodes<D>(tV, T), Cn);
       } else {
