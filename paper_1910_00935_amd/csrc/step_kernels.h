@@ -195,6 +195,16 @@ __device__ __forceinline__ void zero_range(float4* p, long n) {
   for (long q = long(blockIdx.x) * blockDim.x + threadIdx.x; q < n; q += stride) p[q] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// Read of a value that is uniform over the workgroup and was written by an
+// earlier launch (box tables): through the constant address space, so it is a
+// scalar load counted apart from the vector loads issued before it, and its
+// use does not wait for them.
+typedef __attribute__((address_space(4))) const int4 uniform_int4;
+__device__ __forceinline__ int4 load_uniform(const int4* p) {
+  const uniform_int4* q = (const uniform_int4*)(p);
+  return make_int4(q->x, q->y, q->z, q->w);
+}
+
 // (r / d, r % d) for 0 <= r < 2^16 and 1 <= d <= 2^10, with rcp = (1/d)(1 + 2^-20):
 // the product r * rcp then lies in [r/d, floor(r/d) + 1) exactly as in real
 // arithmetic, so its truncation is the quotient.
@@ -266,8 +276,8 @@ __device__ __forceinline__ void clear_entry(const ClearSpec& s0, const ClearSpec
   which = j < m0 ? 0 : 1;
   const int4* t = which == 0 ? s0.box : s1.box;
   const int jj = which == 0 ? j : j - m0;
-  lo = t[2 * jj];
-  ex = t[2 * jj + 1];
+  lo = load_uniform(t + 2 * jj);
+  ex = load_uniform(t + 2 * jj + 1);
 }
 
 __device__ __forceinline__ ClearJobs clear_jobs_fetch(const ClearSpec& s0, const ClearSpec& s1) {
@@ -672,7 +682,7 @@ __device__ __forceinline__ Tile<D> recorded_tile(const int4* table, int wg, int 
                                                  int n) {
   Tile<D> T = empty_tile<D>();
   if (!enabled) return T;
-  const int4 l4 = table[2 * wg], e4 = table[2 * wg + 1];
+  const int4 l4 = load_uniform(table + 2 * wg), e4 = load_uniform(table + 2 * wg + 1);
   const int lo3[3] = {l4.x, l4.y, l4.z}, ex3[3] = {e4.x, e4.y, e4.z};
   int lo[D], ext[D];
   bool inside = true;
@@ -702,8 +712,13 @@ template <int D>
 __device__ __forceinline__ void record_box(int4* table, int index, const Tile<D>& T, int scene) {
   if (!table || threadIdx.x != 0) return;
   const bool any = T.n > 0;
-  table[2 * index] = make_int4(T.lo[0], T.lo[1], D == 3 ? T.lo[2] : 0, scene);
-  table[2 * index + 1] = make_int4(any ? T.ext[0] : 0, any ? T.ext[1] : 0, D == 3 ? (any ? T.ext[2] : 0) : 1, 0);
+  int lo2 = 0, ext2 = 1;  // 2D: a one-node third axis
+  if constexpr (D == 3) {
+    lo2 = T.lo[2];
+    ext2 = any ? T.ext[2] : 0;
+  }
+  table[2 * index] = make_int4(T.lo[0], T.lo[1], lo2, scene);
+  table[2 * index + 1] = make_int4(any ? T.ext[0] : 0, any ? T.ext[1] : 0, ext2, 0);
 }
 
 // Records the union of a tile's box and the stencil-base box `bx` (empty when
@@ -1234,7 +1249,7 @@ struct LaneMap {
     const int per_block = int(blockDim.x) / LPP;
     int end;
     if (k.blocks) {
-      const int4 bi = k.blocks[block_index];
+      const int4 bi = load_uniform(k.blocks + block_index);
       first = bi.x;
       count = bi.y;
       scene = bi.z;
