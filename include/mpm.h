@@ -153,9 +153,11 @@ mpm_status mpm_bind_workspace(mpm_ctx* ctx, void* dev, size_t bytes);
  * that fewer lanes add to one LDS node at a time); "rotate" (0/1, default
  * 1: each lane of a wave visits its 3^d stencil nodes in an order set by its
  * lane index, so lanes rarely add to the same node in the same instruction);
- * "lanes" (1 or 4, default 1: lanes per particle in the step kernels; with
- * 4, three lanes each take one slab of the 3^d stencil and the quad sums its
- * gathers, which raises parallelism for small particle counts);
+ * "lanes" (1, 2 or 4, default 1: lanes per particle in the step kernels;
+ * with 2, each lane of a pair visits half of the 3^d stencil (one in reverse
+ * order) and the pair sums its gathers; with 4, three lanes each take one
+ * slab and the quad sums its gathers; both raise parallelism for small
+ * particle counts);
  * "graph" (0/1, default 1:
  * capture each tape forward/backward launch sequence once in a HIP graph on
  * an internal stream and replay it on the caller's stream; the cache is keyed

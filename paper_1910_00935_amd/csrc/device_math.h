@@ -99,6 +99,12 @@ __device__ __forceinline__ bool state_finite(const PState<D>& p) {
 // step t_a of axis a, the node whose coordinate is congruent to t_a + s_a
 // (mod 3); lanes of different colours therefore never touch the same node in
 // the same instruction. Colour -1 keeps the natural order base, base+1, base+2.
+//
+// Pair mode (two lanes per particle): the second lane of a pair visits every
+// axis in the reverse order (step t_a -> node congruent to 2 - t_a + s_a), so
+// the first H visits of lane 0 and the first H - 1 of lane 1 (H = 14 in 3D,
+// 5 in 2D; the node with flat index H - 1 is lane 0's) split the stencil;
+// skip_last marks lane 1.
 template <int D>
 struct Sten {
   int base[D] = {};
@@ -107,13 +113,14 @@ struct Sten {
   float dN[D][3];
   float dl[D][3];
   int nc[D][3];
+  bool skip_last = false;
 };
 
 // Returns false when the stencil would leave [0, n) on some axis (or x is not
 // finite); base is then 0 so that no caller indexes out of bounds.
 template <int D>
 __device__ __forceinline__ bool make_sten(const float (&x)[D], float inv_dx, float dx, int n, int color,
-                                          Sten<D>& st) {
+                                          Sten<D>& st, bool mirror = false) {
   bool ok = true;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -135,7 +142,7 @@ __device__ __forceinline__ bool make_sten(const float (&x)[D], float inv_dx, flo
     }
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-      int o = t + k;
+      int o = (mirror ? 2 - t : t) + k;
       o = (o >= 3) ? o - 3 : o;
       st.N[a][t] = (o == 0) ? w[0] : ((o == 1) ? w[1] : w[2]);
       st.dN[a][t] = (o == 0) ? dw[0] : ((o == 1) ? dw[1] : dw[2]);
@@ -143,6 +150,7 @@ __device__ __forceinline__ bool make_sten(const float (&x)[D], float inv_dx, flo
       st.nc[a][t] = b + o;
     }
   }
+  st.skip_last = mirror;
   return ok;
 }
 

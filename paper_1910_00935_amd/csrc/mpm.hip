@@ -326,12 +326,20 @@ mpm_status launch_bwd(const mpm_ctx& c, const BwdArgs& a, hipStream_t st) {
 }
 
 mpm_status fwd(const mpm_ctx& c, const FwdArgs& a, hipStream_t st) {
-  if (c.d == 2) return c.lanes == 4 ? launch_fwd<2, 4>(c, a, st) : launch_fwd<2, 1>(c, a, st);
-  return c.lanes == 4 ? launch_fwd<3, 4>(c, a, st) : launch_fwd<3, 1>(c, a, st);
+  if (c.d == 2) {
+    if (c.lanes == 4) return launch_fwd<2, 4>(c, a, st);
+    return c.lanes == 2 ? launch_fwd<2, 2>(c, a, st) : launch_fwd<2, 1>(c, a, st);
+  }
+  if (c.lanes == 4) return launch_fwd<3, 4>(c, a, st);
+  return c.lanes == 2 ? launch_fwd<3, 2>(c, a, st) : launch_fwd<3, 1>(c, a, st);
 }
 mpm_status bwd(const mpm_ctx& c, const BwdArgs& a, hipStream_t st) {
-  if (c.d == 2) return c.lanes == 4 ? launch_bwd<2, 4>(c, a, st) : launch_bwd<2, 1>(c, a, st);
-  return c.lanes == 4 ? launch_bwd<3, 4>(c, a, st) : launch_bwd<3, 1>(c, a, st);
+  if (c.d == 2) {
+    if (c.lanes == 4) return launch_bwd<2, 4>(c, a, st);
+    return c.lanes == 2 ? launch_bwd<2, 2>(c, a, st) : launch_bwd<2, 1>(c, a, st);
+  }
+  if (c.lanes == 4) return launch_bwd<3, 4>(c, a, st);
+  return c.lanes == 2 ? launch_bwd<3, 2>(c, a, st) : launch_bwd<3, 1>(c, a, st);
 }
 
 FwdArgs fwd_args(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
@@ -617,7 +625,7 @@ mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value) {
     return MPM_OK;
   }
   if (k == "lanes") {
-    if (value != 1 && value != 4) return MPM_E_ARG;
+    if (value != 1 && value != 2 && value != 4) return MPM_E_ARG;
     ctx->lanes = int(value);
     return update_blocks(*ctx);
   }

@@ -125,11 +125,29 @@ struct BwdArgs {
   const int4* boxB_in;
 };
 
-// Visits the stencil nodes (t0, t1, t2); S0 = 3 visits all, S0 = 1 only the
-// slab t0 = 0 (the lane's own slab when a quad of lanes shares a particle).
+// Visits the stencil nodes (t0, t1, t2) in the lane's order (see Sten).
+// S0 = 3: all of them; S0 = 1: only the slab t0 = 0 (quad mode: the lane's own
+// slab); S0 = 2: the first H of them in flat order t0 * 9 + t1 * 3 + t2 (pair
+// mode), the last one skipped when st.skip_last.
 template <int D, int S0, class Fn>
-__device__ __forceinline__ void for_nodes(Fn&& fn) {
-  if constexpr (D == 2) {
+__device__ __forceinline__ void for_nodes(const Sten<D>& st, Fn&& fn) {
+  if constexpr (S0 == 2) {
+    constexpr int H = (D == 3) ? 14 : 5;
+#pragma unroll
+    for (int f = 0; f < H - 1; ++f) {
+      if constexpr (D == 3)
+        fn(f / 9, (f / 3) % 3, f % 3);
+      else
+        fn(f / 3, f % 3, 0);
+    }
+    if (!st.skip_last) {
+      constexpr int f = H - 1;
+      if constexpr (D == 3)
+        fn(f / 9, (f / 3) % 3, f % 3);
+      else
+        fn(f / 3, f % 3, 0);
+    }
+  } else if constexpr (D == 2) {
 #pragma unroll
     for (int o0 = 0; o0 < S0; ++o0)
 #pragma unroll
@@ -322,21 +340,34 @@ __device__ __forceinline__ float quad_sum(float v) {
   return v;
 }
 
+// Sum over the two lanes of a pair.
+__device__ __forceinline__ float pair_sum(float v) {
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));  // [1,0,3,2]
+}
+
+// Completes a gather split over the lanes of a particle (S0 as in for_nodes).
+template <int S0>
+__device__ __forceinline__ float lanes_sum(float v) {
+  if constexpr (S0 == 1) return quad_sum(v);
+  if constexpr (S0 == 2) return pair_sum(v);
+  return v;
+}
+
 template <int S0, int N>
 __device__ __forceinline__ void quad_reduce(float (&v)[N]) {
-  if constexpr (S0 == 1) {
+  if constexpr (S0 != 3) {
 #pragma unroll
-    for (int q = 0; q < N; ++q) v[q] = quad_sum(v[q]);
+    for (int q = 0; q < N; ++q) v[q] = lanes_sum<S0>(v[q]);
   }
 }
 
 template <int S0, int N, int M>
 __device__ __forceinline__ void quad_reduce(float (&v)[N][M]) {
-  if constexpr (S0 == 1) {
+  if constexpr (S0 != 3) {
 #pragma unroll
     for (int q = 0; q < N; ++q)
 #pragma unroll
-      for (int r = 0; r < M; ++r) v[q][r] = quad_sum(v[q][r]);
+      for (int r = 0; r < M; ++r) v[q][r] = lanes_sum<S0>(v[q][r]);
   }
 }
 
@@ -508,7 +539,7 @@ __device__ __forceinline__ int lane_color(const StepConsts& k) {
 // Stencil of the particle at x for this lane (quad mode: the lane's slab).
 template <int D, int LPP>
 __device__ __forceinline__ bool lane_sten(const StepConsts& k, const float (&x)[D], int sub, Sten<D>& st) {
-  const bool ok = make_sten<D>(x, k.inv_dx, k.dx, k.n, lane_color<D, LPP>(k), st);
+  const bool ok = make_sten<D>(x, k.inv_dx, k.dx, k.n, lane_color<D, LPP>(k), st, LPP == 2 && sub == 1);
   if constexpr (LPP == 4) slab_select<D>(st, sub);
   return ok;
 }
@@ -906,7 +937,7 @@ __device__ __forceinline__ void node_vel(const StepConsts& k, const Sten<D>& st,
 template <int D, bool L, int S0>
 __device__ __forceinline__ void g2p_body(const StepConsts& k, const Sten<D>& st, const Nodes<D, L>& g, PState<D>& p) {
   float vn[D] = {}, Cn[D][D] = {};
-  for_nodes<D, S0>([&](int o0, int o1, int o2) {
+  for_nodes<D, S0>(st, [&](int o0, int o1, int o2) {
     const float w = wgt<D>(st, o0, o1, o2);
     float dl[D], v[D];
     delta<D>(st, o0, o1, o2, k.dx, dl);
@@ -950,7 +981,7 @@ __device__ __forceinline__ void g2p_body(const StepConsts& k, const Sten<D>& st,
 template <int D, int S0, class SA>
 __device__ __forceinline__ void p2g_body(const StepConsts& k, const Sten<D>& st, float mass, const float (&mv)[D],
                                          const float (&A)[D][D], const SA& g) {
-  for_nodes<D, S0>([&](int o0, int o1, int o2) {
+  for_nodes<D, S0>(st, [&](int o0, int o1, int o2) {
     const float w = wgt<D>(st, o0, o1, o2);
     float dl[D];
     delta<D>(st, o0, o1, o2, k.dx, dl);
@@ -1077,7 +1108,7 @@ __device__ __forceinline__ void p2g_adj_body(const StepConsts& k, const Sten<D>&
                                              const float (&A)[D][D], const Nodes<D, L>& g, const Nodes<D, L>& ad,
                                              float (&gx)[D], float (&vb)[D], float (&Abar)[D][D]) {
   float gxa[D] = {};
-  for_nodes<D, S0>([&](int o0, int o1, int o2) {
+  for_nodes<D, S0>(st, [&](int o0, int o1, int o2) {
     float Pb[D], mb;
     node_adj<D>(k, st, o0, o1, o2, g, ad, Pb, mb);
     const float w = wgt<D>(st, o0, o1, o2);
@@ -1117,7 +1148,7 @@ __device__ __forceinline__ void g2p_C(const StepConsts& k, const Sten<D>& st, co
   for (int c = 0; c < D; ++c)
 #pragma unroll
     for (int b = 0; b < D; ++b) Cn[c][b] = 0.0f;
-  for_nodes<D, S0>([&](int o0, int o1, int o2) {
+  for_nodes<D, S0>(st, [&](int o0, int o1, int o2) {
     const float w = wgt<D>(st, o0, o1, o2);
     float dl[D], v[D];
     delta<D>(st, o0, o1, o2, k.dx, dl);
@@ -1140,7 +1171,7 @@ __device__ __forceinline__ void g2p_adj_body(const StepConsts& k, const Sten<D>&
                                              const float (&Bm)[D][D], const GA& g, const SA& ad, float (&px)[D],
                                              bool scatter) {
   float pxa[D] = {};
-  for_nodes<D, S0>([&](int o0, int o1, int o2) {
+  for_nodes<D, S0>(st, [&](int o0, int o1, int o2) {
     float v[D];
     node_vel<D>(k, st, o0, o1, o2, g, v);
     const float w = wgt<D>(st, o0, o1, o2);
@@ -1190,7 +1221,7 @@ template <int D, int LPP>
 __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i, int sc, bool one_scene, int sub,
                                           int count, const PState<D>& p, const float* act_row, float4* grid,
                                           long long* tile, BlockRed& rd, unsigned& err, int4* box_out, int wg) {
-  constexpr int S0 = (LPP == 4) ? 1 : 3;
+  constexpr int S0 = (LPP == 4) ? 1 : (LPP == 2 ? 2 : 3);
   Sten<D> st;
   const bool fin = live && state_finite<D>(p);
   const bool ok = fin && lane_sten<D, LPP>(k, p.x, sub, st);
@@ -1211,7 +1242,7 @@ __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i,
   const Tile<D> T = block_tile_scaled<D>(ok, st.base, bound, count, one_scene, k.lds, rd);
   record_box<D>(box_out, wg, T, one_scene ? sc : -1);
   float4* g = grid + long(sc) * k.nodes;
-  if (ok && (LPP == 1 || sub < 3)) {
+  if (ok && (LPP != 4 || sub < 3)) {
     if (T.on)
       p2g_body<D, S0>(k, st, mass, mv, A, fix_nodes<D>(tile, T));
     else
@@ -1234,9 +1265,11 @@ __device__ __forceinline__ void zero_tile64(long long* tile) {
 // Kernels
 // ---------------------------------------------------------------------------
 // Thread -> particle mapping. LPP = 1: one lane per particle (optionally
-// interleaved, lane_particle). LPP = 4: a quad of lanes per particle; lanes
+// interleaved, lane_particle). LPP = 2: a pair of lanes per particle, each
+// visiting half of the stencil (see Sten and for_nodes); gathers are completed
+// with one DPP add per value. LPP = 4: a quad of lanes per particle; lanes
 // 0..2 each take one slab of the stencil (t0 = 0, 1, 2), lane 3 only joins
-// the quad reductions; lane 0 of the quad writes the particle's outputs.
+// the quad reductions. Lane 0 of a pair or quad writes the particle's outputs.
 //
 // With several scenes, workgroups are scene-aligned: k.blocks[b] = (first
 // particle, particle count, scene) of workgroup b, so every workgroup holds one
@@ -1263,6 +1296,9 @@ struct LaneMap {
     if constexpr (LPP == 4) {
       sub = int(threadIdx.x & 3);
       i = first + int(threadIdx.x >> 2);
+    } else if constexpr (LPP == 2) {
+      sub = int(threadIdx.x & 1);
+      i = first + int(threadIdx.x >> 1);
     } else {
       sub = 0;
       i = first + lane_particle(threadIdx.x, blockDim.x, k.remap);
@@ -1274,7 +1310,7 @@ struct LaneMap {
 
 template <int D, int LPP>
 __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
-  constexpr int S0 = (LPP == 4) ? 1 : 3;
+  constexpr int S0 = (LPP == 4) ? 1 : (LPP == 2 ? 2 : 3);
   __shared__ long long tile64[(D + 1) * kTileMax];  // P2G scatter tile (fixed point)
   __shared__ float vtile[D * kTileMax];              // G2P velocity tile
   __shared__ int red[64];
@@ -1347,7 +1383,7 @@ __device__ __forceinline__ void wave_add_keyed(bool live, int key, double val, d
 
 template <int D, int LPP>
 __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
-  constexpr int S0 = (LPP == 4) ? 1 : 3;
+  constexpr int S0 = (LPP == 4) ? 1 : (LPP == 2 ? 2 : 3);
   __shared__ float tA[(D + 1) * kTileMax];      // phase A: adjoint tile (P*, m*)
   __shared__ float tV[D * kTileMax];            // phase B: velocity tile
   __shared__ long long tS[(D + 1) * kTileMax];  // scatter tile: phase B (adjoint grid), phase C (grid)
@@ -1603,7 +1639,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     record_box_union<D>(a.boxB, wg, T, outside, one_scene ? sc : -1);
     const bool fix = T.on && e_fix != INT_MIN;
     if (ok) {
-      const bool scatter = LPP == 1 || sub < 3;
+      const bool scatter = LPP != 4 || sub < 3;
       if (in_t && fix) {
         FixNodes<D> fn = fix_nodes<D>(tS, T);
         fn.e = e_fix;

@@ -34,7 +34,7 @@ def test_c1_closed_form_and_oracle():
     compare("c1", sc, g, o, grads=("v",), check_E=False)
 
 
-@pytest.mark.parametrize("lanes", [1, 4])
+@pytest.mark.parametrize("lanes", [1, 2, 4])
 def test_c1d_parity(lanes):
     """Deforming 2D body: mean-x loss gradients, then a random functional of the
     final state for every input block and E."""
@@ -56,6 +56,7 @@ def c3_oracle_64():
 
 
 @pytest.mark.parametrize("knobs", [dict(block=64), dict(block=128), dict(block=256), dict(block=128, lanes=4),
+                                   dict(block=256, lanes=2), dict(block=64, lanes=2, rotate=0),
                                    dict(block=256, lanes=4, rotate=0), dict(block=128, lds=0, remap=1)])
 def test_c3_parity_64_steps(knobs, c3_oracle_64):
     """3D workload c3 (64^3 grid, 32768 particles) gated at 64 steps, in each
@@ -74,7 +75,7 @@ def test_checkpointed_matches_oracle():
     compare("c1d@20 K=4", sc, g, o, grads=("x", "v", "C", "F"))
 
 
-@pytest.mark.parametrize("lanes", [1, 4])
+@pytest.mark.parametrize("lanes", [1, 2, 4])
 def test_c5_batched_subset(lanes):
     """A few scenes of the batched workload run as one batch. The bodies start
     at rest, so until they reach the floor (about step 100) they fall rigidly

@@ -26,7 +26,7 @@ def _case(dim, n_keep):
     return scenes.random_state(base, seed=10 + dim)
 
 
-@pytest.mark.parametrize("lanes", [1, 4])
+@pytest.mark.parametrize("lanes", [1, 2, 4])
 @pytest.mark.parametrize("dim,n_keep", [(2, 1024), (2, 777), (3, 4099)])
 def test_step_fwd_matches_oracle(dim, n_keep, lanes):
     sc = _case(dim, n_keep)
@@ -48,7 +48,7 @@ def test_step_fwd_matches_oracle(dim, n_keep, lanes):
     assert r[0] < 2e-7 and max(r[1:]) < 2e-5, r
 
 
-@pytest.mark.parametrize("lanes", [1, 4])
+@pytest.mark.parametrize("lanes", [1, 2, 4])
 @pytest.mark.parametrize("dim,n_keep", [(2, 1024), (2, 777), (3, 4099)])
 def test_step_bwd_matches_oracle(dim, n_keep, lanes):
     sc = _case(dim, n_keep)
