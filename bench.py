@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fwd+bwd particle-steps/s, 3D MLS-MPM 64³ grid; batched vs per-scene launches"
 HBM_PEAK_GBS = 8000.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_c3.json")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_elastic3d.json")
 
 
 def _source_hash():
@@ -69,8 +69,8 @@ def tuned_knobs(scene, args, pinned=None):
     return autotune.tune(scene, cache=args.tune_cache, steps=min(scene.steps, 64))
 
 
-def run_c3(args, torch, rt, scenes):
-    sc = scenes.c3()
+def run_elastic3d(args, torch, rt, scenes):
+    sc = scenes.elastic3d()
     T = sc.steps
     N = sc.n_particles
     knobs = tuned_knobs(sc, args, json.loads(args.knobs) if args.knobs else None)
@@ -176,7 +176,7 @@ def _pmc_means(csv_path, counter):
 
 
 def summarize_pmc(fetch_csv, write_csv, knobs, command):
-    """profiles/traffic_c3.json from a FETCH_SIZE run and a WRITE_SIZE run of
+    """profiles/traffic_elastic3d.json from a FETCH_SIZE run and a WRITE_SIZE run of
     `bench.py --profile`: per-dispatch KiB of the step kernels, each scaled by
     the ratio of the calibration copy's known size to its own reading."""
     fetch, n_f, copy_f = _pmc_means(fetch_csv, "FETCH_SIZE")
@@ -207,7 +207,7 @@ def run_cpu_baseline(sample_steps):
     import numpy as np  # noqa: F401
     import oracle as orc
     from paper_1910_00935_amd import scenes
-    sc = scenes.c3()
+    sc = scenes.elastic3d()
     st = orc.pack(sc.x, sc.v, sc.C, sc.F)
     t0 = time.perf_counter()
     sT, _, _ = orc.run_fwd(sc, sample_steps, st)
@@ -222,7 +222,7 @@ def run_cpu_baseline(sample_steps):
 def run_batched(args, torch, rt, scenes, n_scenes=256, steps=256):
     """2D workload of `n_scenes` independent scenes: one context (one launch per
     step for all scenes) against one context per scene run back to back."""
-    sc = scenes.c5(n_scenes=n_scenes, steps=steps)
+    sc = scenes.batched2d(n_scenes=n_scenes, steps=steps)
     N = sc.n_particles
     knobs = tuned_knobs(sc, args)
     # One configuration for every per-scene run, tuned on a median-size scene.
@@ -283,6 +283,8 @@ def main():
     ap.add_argument("--knobs", default=None, help='launch configuration for the 3D workload as JSON, e.g. \'{"block": 256}\'')
     ap.add_argument("--profile", action="store_true",
                     help="3D workload only, then one calibration copy (for rocprofv3 counter runs)")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="batched 2D workload only (--steps trajectories), then one calibration copy")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic record from two rocprofv3 --pmc runs of --profile")
     ap.add_argument("--pmc-command", default="", help="command recorded with --summarize-pmc")
@@ -302,20 +304,40 @@ def main():
     from paper_1910_00935_amd import runtime as rt
     from paper_1910_00935_amd import scenes
     torch.cuda.set_device(0)
+    if args.profile_batched:
+        # One batched 2D trajectory (fwd + loss + bwd) per step, for rocprofv3 runs.
+        sc = scenes.batched2d()
+        knobs = tuned_knobs(sc, args, json.loads(args.knobs) if args.knobs else None)
+        sim = rt.Simulator.for_scene(sc, knobs=knobs)
+        p = rt.params_for_scene(sc)
+        init = rt.state_for_scene(sc)
+        tape = sim.tape(sc.steps, 0)
+        fin = rt.State.empty(2, sc.n_particles)
+        seed = rt.State.empty(2, sc.n_particles)
+        g = rt.State.zeros(2, sc.n_particles)
+        gE = torch.zeros(sc.n_scenes, device="cuda")
+        for _ in range(args.steps):
+            tape.forward(p, init, fin)
+            sim.loss_mean(fin, sc.loss_axis, sc.loss_sign, seed)
+            tape.backward(p, seed, g, gE)
+        torch.cuda.synchronize()
+        calibration_copy(torch)
+        print(json.dumps({"profile": "batched 2D", "knobs": knobs, "flags": sim.check_errors()}), flush=True)
+        return
     print("[bench] 3D workload", flush=True)
-    c3 = run_c3(args, torch, rt, scenes)
+    elastic3d = run_elastic3d(args, torch, rt, scenes)
     out = {
-        "metric": METRIC, "value": round(c3["value"], 1), "unit": "particle-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(c3["ms_per_step"], 3),
+        "metric": METRIC, "value": round(elastic3d["value"], 1), "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elastic3d["ms_per_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "3D MLS-MPM fwd+bwd: 64^3 grid, dx=1/64, 32768 particles (jittered 32^3 lattice "
                                "spaced dx/2), neo-Hookean E=20 nu=0.3, dt=5e-4, 256 steps, full tape, "
                                "loss = mean final height; one bench step = one trajectory",
-                   "particles": c3["N"], "time_steps": c3["T"]},
-        "roofline": c3["roofline"],
-        "whole_step_hbm_frac": c3["whole_step_hbm_frac"],
+                   "particles": elastic3d["N"], "time_steps": elastic3d["T"]},
+        "roofline": elastic3d["roofline"],
+        "whole_step_hbm_frac": elastic3d["whole_step_hbm_frac"],
     }
-    out["config"]["knobs"] = c3["knobs"]
+    out["config"]["knobs"] = elastic3d["knobs"]
     if args.profile:
         calibration_copy(torch)
         print(json.dumps(out), flush=True)

@@ -27,11 +27,12 @@
 //
 // LDS scatters accumulate in 64-bit fixed point with integer LDS atomics
 // (ds_add_u64): on gfx950 ds_add_f32 sustains ~0.3 lane-ops per clock per CU
-// against ~14 for ds_add_u32. Each workgroup reduces a bound B on |contribution|
-// over its particles and uses the scale 2^e with count * B < 2^(62 - e), so no
-// node sum can overflow and the rounding error per node stays below
-// count * B * 2^-62 (finer than FP32 accumulation); the flush converts each
-// node back to float once.
+// against ~8 for ds_add_u64 and ~14 for ds_add_u32. Each workgroup reduces a
+// bound B on |contribution| over its particles and uses the scale 2^e with
+// B 2^e < 2^31: every contribution rounds to a 32-bit integer (error below
+// B 2^-31, finer than the FP32 rounding of a partial sum), node sums cannot
+// overflow 64 bits, and the accumulation does not depend on atomic order; the
+// flush converts each node back to float once.
 #pragma once
 
 #include <climits>
@@ -371,19 +372,12 @@ __device__ __forceinline__ void quad_reduce(float (&v)[N][M]) {
   }
 }
 
-// v * 2^e as a 64-bit integer from single-precision operations only (all
-// full rate): the high word is h = round(v 2^(e-32)), the low word the
-// remainder v 2^e - h 2^32, which lies in [-2^31, 2^31] and is exact in
-// single precision; both are converted by truncation. The result is within
-// one unit of v 2^e (within 128 units when v 2^(e-32) lies exactly halfway
-// between two integers). Callers guarantee |v| 2^e < 2^62.
-__device__ __forceinline__ long long to_fixed(float v, int e) {
-  const float x = ldexpf(v, e);
-  const float hf = rintf(ldexpf(v, e - 32));
-  const float r = fminf(fmaf(-hf, 4294967296.0f, x), 2147483520.0f);  // keep int(r) in range
-  const int hi = int(hf), lo = int(r);
-  return (long long)(((unsigned long long)unsigned(hi + (lo >> 31)) << 32) | unsigned(lo));
-}
+// v * 2^e rounded to the nearest integer, as a 64-bit value. The scale is
+// chosen (fixed_exponent) so that |v| 2^e < 2^31 for every contribution, so
+// rounding and conversion are two single-precision instructions and the high
+// word is the sign extension; node sums of up to 2^32 contributions cannot
+// overflow 64 bits.
+__device__ __forceinline__ long long to_fixed(float v, int e) { return (long long)int(rintf(ldexpf(v, e))); }
 
 __device__ __forceinline__ float from_fixed(long long q, int e) {
   const double hi = double(int(q >> 32)) * 4294967296.0;
@@ -557,13 +551,15 @@ __device__ __forceinline__ int lane_particle(int t, int B, int remap) {
   return (t % rows) * 8 + t / rows;
 }
 
-// Fixed-point exponent for `count` contributions bounded by `bmax`: the
-// largest e with count * bmax < 2^(62 - e); INT_MIN when the bound is not finite.
-__device__ __forceinline__ int fixed_exponent(float bmax, int count) {
-  const float total = bmax * float(count);
-  if (!(total < 3.0e38f)) return INT_MIN;
-  if (total <= 0.0f) return 0;
-  return 62 - (ilogbf(total) + 1);
+// Fixed-point exponent for contributions bounded by `bmax`: the largest e
+// with bmax 2^e < 2^31, so each contribution is rounded to a multiple of
+// 2^-e <= bmax 2^-30 (an error below bmax 2^-31, finer than the 2^-24
+// relative rounding of an FP32 partial sum of such contributions); INT_MIN
+// when the bound is not finite.
+__device__ __forceinline__ int fixed_exponent(float bmax) {
+  if (!(bmax < 3.0e38f)) return INT_MIN;
+  if (bmax <= 0.0f) return 0;
+  return 30 - ilogbf(bmax);
 }
 
 // Block-wide reductions with one barrier each: every wave writes its partial
@@ -686,23 +682,14 @@ __device__ __forceinline__ Tile<D> block_tile(bool valid, const int (&base)[D], 
 
 // Box and fixed-point exponent of a scatter tile in one reduction.
 template <int D>
-__device__ __forceinline__ Tile<D> block_tile_scaled(bool valid, const int (&base)[D], float bound, int count,
-                                                     bool one_scene, int enabled, BlockRed& r) {
+__device__ __forceinline__ Tile<D> block_tile_scaled(bool valid, const int (&base)[D], float bound, bool one_scene,
+                                                     int enabled, BlockRed& r) {
   if (!enabled) return empty_tile<D>();
   const Box<D> bx = block_reduce<D>(valid, base, bound, r);
   Tile<D> T = tile_of<D>(bx, one_scene);
-  T.e = fixed_exponent(bx.bmax, count);
+  T.e = fixed_exponent(bx.bmax);
   T.on = T.on && T.e != INT_MIN;
   return T;
-}
-
-// Fixed-point exponent alone (all threads call).
-template <int D>
-__device__ __forceinline__ int block_scale(float bound, int count, BlockRed& r) {
-  int none[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) none[a] = 0;
-  return fixed_exponent(block_reduce<D>(false, none, bound, r).bmax, count);
 }
 
 // The box a gather needs, as recorded by the scatter into the same grid one
@@ -1219,7 +1206,7 @@ __device__ __forceinline__ int actuator_of(const StepConsts& k, const float* act
 // components (zero_tile64).
 template <int D, int LPP>
 __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i, int sc, bool one_scene, int sub,
-                                          int count, const PState<D>& p, const float* act_row, float4* grid,
+                                          const PState<D>& p, const float* act_row, float4* grid,
                                           long long* tile, BlockRed& rd, unsigned& err, int4* box_out, int wg) {
   constexpr int S0 = (LPP == 4) ? 1 : (LPP == 2 ? 2 : 3);
   Sten<D> st;
@@ -1239,7 +1226,7 @@ __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i,
     mass = sp.mass;
     bound = p2g_bound<D>(mass, mv, A, k.dx);
   }
-  const Tile<D> T = block_tile_scaled<D>(ok, st.base, bound, count, one_scene, k.lds, rd);
+  const Tile<D> T = block_tile_scaled<D>(ok, st.base, bound, one_scene, k.lds, rd);
   record_box<D>(box_out, wg, T, one_scene ? sc : -1);
   float4* g = grid + long(sc) * k.nodes;
   if (ok && (LPP != 4 || sub < 3)) {
@@ -1361,7 +1348,7 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
     clear_jobs_run<D>(cj, c0, c1, k.n, k.nodes, k.n_scenes);
   }
   if (a.do_p2g)
-    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_row, a.grid_out, tile64, rd, err, a.box_out,
+    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_row, a.grid_out, tile64, rd, err, a.box_out,
                       int(blockIdx.x));
   if (err) atomicOr(k.err, err);
 }
@@ -1410,7 +1397,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     PState<D> p;
     if (live) load_state<D>(a.stC, i, p);
     clear_jobs_run<D>(cj, c0, c1, k.n, k.nodes, k.n_scenes);
-    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
+    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
     if (err) atomicOr(k.err, err);
     return;
   }
@@ -1628,7 +1615,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     Box<D> outside;
     if (k.lds) {
       outside = block_reduce<D>(ok && !in_t, st.base, bound, rd);
-      e_fix = fixed_exponent(outside.bmax, lm.count);
+      e_fix = fixed_exponent(outside.bmax);
     } else {
 #pragma unroll
       for (int c = 0; c < D; ++c) {
@@ -1672,7 +1659,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     if (live) load_state<D>(a.stC, i, p);
     __syncthreads();  // every thread is done with the scatter tile of phase B
     if (k.lds) zero_tile64<D + 1>(tS);
-    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, lm.count, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
+    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
   }
   if (err) atomicOr(k.err, err);
 }

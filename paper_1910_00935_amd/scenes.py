@@ -11,13 +11,13 @@ so parity measures the dynamics and not input rounding.
 
 Workloads (the paper's elastic-object simulator, Section 4.1; its own
 benchmark used a 2D scene with 6.4K particles whose grid is not stated):
-  c1   2D, 64^2 grid, 1024 particles on a jittered lattice, uniform v=(1,0), 64 steps
-  c1d  c1 with an added affine velocity, so the body deforms
-  c2   2D actuated soft body, 128^2 grid, 8192 particles in a union of rectangles,
+  translate2d   2D, 64^2 grid, 1024 particles on a jittered lattice, uniform v=(1,0), 64 steps
+  deform2d  translate2d with an added affine velocity, so the body deforms
+  actuated2d   2D actuated soft body, 128^2 grid, 8192 particles in a union of rectangles,
        4 actuators driven by a_k(t) = tanh(sum_j W_kj sin(w t + 2 pi j/4) + b_k), 512 steps
-  c3   3D, 64^3 grid, 32768 particles on a 32^3 jittered lattice, 256 steps, full tape
-  c4   3D, 128^3 grid, 262144 particles on a 64^3 lattice, 1024 steps, checkpoints every 64
-  c5   256 independent 2D scenes on their own 64^2 grids, particle counts
+  elastic3d   3D, 64^3 grid, 32768 particles on a 32^3 jittered lattice, 256 steps, full tape
+  elastic3d_long   3D, 128^3 grid, 262144 particles on a 64^3 lattice, 1024 steps, checkpoints every 64
+  batched2d   256 independent 2D scenes on their own 64^2 grids, particle counts
        log-uniform in [500, 8000], per-scene E and nu, 256 steps
   fd8  8 particles with random C and F, for finite-difference checks
 """
@@ -109,7 +109,7 @@ def _single(name, dim, n_grid, dt, steps, x, v, E, nu, vol, **kw):
         x=_f32(x), v=_f32(v), C=_f32(np.zeros((N, dim, dim))), F=_f32(_identity(N, dim)), **kw)
 
 
-def c1(seed: int = 0) -> Scene:
+def translate2d(seed: int = 0) -> Scene:
     """2D, 64^2, 1024 particles on a 32x32 lattice spaced dx/2 in [0.25, 0.5]^2,
     jitter U(+-0.1 dx), v = (1, 0), E = 10, nu = 0.2, volume (dx/2)^2, dt = 1e-3, 64 steps,
     loss = mean final x-coordinate."""
@@ -118,15 +118,15 @@ def c1(seed: int = 0) -> Scene:
     dx = 1.0 / n
     x = _lattice(rng, 2, 32, 0.25, dx / 2, 0.1 * dx)
     v = np.tile([1.0, 0.0], (x.shape[0], 1))
-    return _single("c1", 2, n, 1e-3, 64, x, v, 10.0, 0.2, (dx / 2) ** 2, loss_axis=0)
+    return _single("translate2d", 2, n, 1e-3, 64, x, v, 10.0, 0.2, (dx / 2) ** 2, loss_axis=0)
 
 
-def c1d(seed: int = 0) -> Scene:
-    """c1 with v = (1, 0) + diag(1, -1) (x - (0.375, 0.375)) so that C and F evolve."""
-    s = c1(seed)
+def deform2d(seed: int = 0) -> Scene:
+    """translate2d with v = (1, 0) + diag(1, -1) (x - (0.375, 0.375)) so that C and F evolve."""
+    s = translate2d(seed)
     x = s.x.astype(np.float64)
     v = np.array([1.0, 0.0]) + (x - 0.375) * np.array([1.0, -1.0])
-    return replace(s, name="c1d", v=_f32(v))
+    return replace(s, name="deform2d", v=_f32(v))
 
 
 def _skyline_rects(rng, n_rect, w_lo, w_hi, h_lo, h_hi, x_lo, x_hi):
@@ -176,7 +176,7 @@ def _sample_union(rng, rects, N):
     return np.concatenate(pts), np.concatenate(ids)
 
 
-def c2(seed: int = 1) -> Scene:
+def actuated2d(seed: int = 1) -> Scene:
     """2D actuated soft body: 128^2 grid, 8192 particles uniform in a union of 4-6
     rectangles (widths, heights U[0.05, 0.2], standing on y = 0.1, x in [0.1, 0.6]);
     actuator column = (first containing rectangle) mod 4; a_k(t) = tanh(sum_j W_kj
@@ -192,14 +192,14 @@ def c2(seed: int = 1) -> Scene:
     n_act = 4
     W = rng.normal(0.0, 0.1, size=(n_act, 4))
     b = rng.normal(0.0, 0.1, size=(n_act,))
-    s = _single("c2", 2, n, 1e-3, 512, pts, np.zeros((N, 2)), 10.0, 0.2, area / N, loss_axis=0,
+    s = _single("actuated2d", 2, n, 1e-3, 512, pts, np.zeros((N, 2)), 10.0, 0.2, area / N, loss_axis=0,
                 loss_sign=-1.0, act_id=(first % n_act).astype(np.int32), n_act=n_act, act_strength=10.0,
                 act_W=_f32(W), act_b=_f32(b), act_omega=float(F32(2 * math.pi * 5)))
     s.meta["rects"] = rects
     return s
 
 
-def _c3_like(name, seed, n_grid, per_axis, dt, steps, ckpt, loss_axis):
+def _lattice3d(name, seed, n_grid, per_axis, dt, steps, ckpt, loss_axis):
     rng = np.random.default_rng(seed)
     dx = 1.0 / n_grid
     x = _lattice(rng, 3, per_axis, 0.25, dx / 2, 0.1 * dx)
@@ -209,19 +209,19 @@ def _c3_like(name, seed, n_grid, per_axis, dt, steps, ckpt, loss_axis):
                    loss_axis=loss_axis)
 
 
-def c3(seed: int = 2) -> Scene:
+def elastic3d(seed: int = 2) -> Scene:
     """3D, 64^3 grid, 32768 particles on a 32^3 lattice spaced dx/2 in [0.25, 0.5]^3,
     jittered, E = 20, nu = 0.3, dt = 5e-4, 256 steps, full tape; loss = mean final height."""
-    return _c3_like("c3", seed, 64, 32, 5e-4, 256, 0, 1)
+    return _lattice3d("elastic3d", seed, 64, 32, 5e-4, 256, 0, 1)
 
 
-def c4(seed: int = 3) -> Scene:
+def elastic3d_long(seed: int = 3) -> Scene:
     """3D, 128^3 grid, 262144 particles on a 64^3 lattice spaced dx/2, jittered, E = 20,
     nu = 0.3, dt = 2.5e-4, 1024 steps, checkpoints every 64; loss = mean final x."""
-    return _c3_like("c4", seed, 128, 64, 2.5e-4, 1024, 64, 0)
+    return _lattice3d("elastic3d_long", seed, 128, 64, 2.5e-4, 1024, 64, 0)
 
 
-def c5(seed: int = 4, n_scenes: int = 256, steps: int = 256) -> Scene:
+def batched2d(seed: int = 4, n_scenes: int = 256, steps: int = 256) -> Scene:
     """n_scenes independent 2D scenes, each on its own 64^2 grid, with particle counts
     N = round(exp U(ln 500, ln 8000)) in rectangle-union shapes (4 particles per cell,
     volume (dx/2)^2), centred in x and standing on y = 0.1; E ~ U[5, 30], nu ~ U[0.1, 0.4];
@@ -259,7 +259,7 @@ def c5(seed: int = 4, n_scenes: int = 256, steps: int = 256) -> Scene:
     off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
     ns = n_scenes
     return Scene(
-        name="c5", dim=2, n_grid=n, dx=dx, dt=float(F32(1e-3)), steps=steps, offsets=off, E=_f32(Es),
+        name="batched2d", dim=2, n_grid=n, dx=dx, dt=float(F32(1e-3)), steps=steps, offsets=off, E=_f32(Es),
         nu=_f32(nus), vol=_f32(np.full(ns, vol)), rho=_f32(np.ones(ns)), x=_f32(x),
         v=_f32(np.zeros((Nt, 2))), C=_f32(np.zeros((Nt, 2, 2))), F=_f32(_identity(Nt, 2)), loss_axis=0)
 
@@ -291,7 +291,7 @@ def random_state(scene: Scene, seed: int, c_scale: float = 1.0, f_scale: float =
                    F=_f32(np.eye(d) + f_scale * rng.normal(0, 1, (N, d, d))))
 
 
-REGISTRY = {"c1": c1, "c1d": c1d, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+REGISTRY = {"translate2d": translate2d, "deform2d": deform2d, "actuated2d": actuated2d, "elastic3d": elastic3d, "elastic3d_long": elastic3d_long, "batched2d": batched2d}
 
 
 def make(name: str, **kw) -> Scene:

@@ -10,9 +10,9 @@ def test_candidates_cover_the_space():
 
 
 def test_shape_key_depends_on_shape_only():
-    a = scenes.c1()
-    b = scenes.c1(seed=7)          # same shape, other values
-    c = scenes.c1d().with_steps(32)  # other horizon
+    a = scenes.translate2d()
+    b = scenes.translate2d(seed=7)          # same shape, other values
+    c = scenes.deform2d().with_steps(32)  # other horizon
     assert autotune.shape_key(a, "gfx950") == autotune.shape_key(b, "gfx950")
     assert autotune.shape_key(a, "gfx950") != autotune.shape_key(c, "gfx950")
     assert autotune.shape_key(a, "gfx950") != autotune.shape_key(a, "gfx942")

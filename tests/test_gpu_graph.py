@@ -31,7 +31,7 @@ def _run(sim, sc, tape, p, init, w, repeats=1):
 
 @pytest.mark.parametrize("K", [0, 4])
 def test_graph_replay_matches_direct_launches(K):
-    sc = scenes.c1d().with_steps(24)
+    sc = scenes.deform2d().with_steps(24)
     w = random_seed(sc, 3)
     p = rt.params_for_scene(sc)
     init = rt.state_for_scene(sc)
@@ -50,7 +50,7 @@ def test_graph_replay_matches_direct_launches(K):
 def test_graph_repeated_backward_and_recapture():
     """Two backward passes after one forward (checkpointed: the second starts from
     a different ring state), then new state buffers (a new capture)."""
-    sc = scenes.c1d().with_steps(20)
+    sc = scenes.deform2d().with_steps(20)
     w = random_seed(sc, 4)
     p = rt.params_for_scene(sc)
     sim = rt.Simulator.for_scene(sc)
@@ -80,7 +80,7 @@ def test_autotune_picks_and_caches(tmp_path):
     """The autotuner times each candidate, returns one of them, and reuses the
     cached answer for the same workload shape."""
     from paper_1910_00935_amd import autotune
-    sc = scenes.c1d().with_steps(8)
+    sc = scenes.deform2d().with_steps(8)
     space = {"block": (128, 64), "lanes": (1, 4), "rotate": (1,), "lds": (1,), "split": (1,)}
     cache = str(tmp_path / "tune.json")
     best = autotune.tune(sc, cache=cache, space=space)
@@ -95,7 +95,7 @@ def test_launch_shape_change_between_trajectories():
     """One context, the launch shape changed between trajectories (the number
     of workgroups, hence the per-workgroup scatter boxes the reverse pass
     clears, changes): same trajectory and gradients as a fresh context."""
-    sc = scenes.c1d().with_steps(24)
+    sc = scenes.deform2d().with_steps(24)
     w = random_seed(sc, 5)
     p = rt.params_for_scene(sc)
     init = rt.state_for_scene(sc)

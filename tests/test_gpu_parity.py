@@ -13,12 +13,12 @@ from parity import act_table, compare, gpu_run, log, oracle_run, random_seed, re
 pytestmark = pytest.mark.gpu
 
 
-def test_c1_closed_form_and_oracle():
-    """c1 is a rigid translation: every particle moves by (T dt, g dt^2 T(T+1)/2),
+def test_translate2d_closed_form_and_oracle():
+    """translate2d is a rigid translation: every particle moves by (T dt, g dt^2 T(T+1)/2),
     dL/dv0 summed = (T dt, 0), dL/dE = 0."""
-    sc = scenes.c1()
+    sc = scenes.translate2d()
     T = sc.steps
-    log(f"[c1] N={sc.n_particles} T={T}")
+    log(f"[translate2d] N={sc.n_particles} T={T}")
     g = gpu_run(sc, T)
     assert g["flags"] == 0
     shift = g["final"][0] - sc.x.astype(np.float64)
@@ -31,62 +31,62 @@ def test_c1_closed_form_and_oracle():
     np.testing.assert_allclose(gv_sum, [T * dt, 0.0], rtol=1e-4, atol=1e-6)
     assert abs(g["gE"][0]) < 1e-6
     o = oracle_run(sc, T)
-    compare("c1", sc, g, o, grads=("v",), check_E=False)
+    compare("translate2d", sc, g, o, grads=("v",), check_E=False)
 
 
 @pytest.mark.parametrize("lanes", [1, 2, 4])
-def test_c1d_parity(lanes):
+def test_deform2d_parity(lanes):
     """Deforming 2D body: mean-x loss gradients, then a random functional of the
     final state for every input block and E."""
-    sc = scenes.c1d()
+    sc = scenes.deform2d()
     g = gpu_run(sc, sc.steps, knobs={"lanes": lanes})
     o = oracle_run(sc, sc.steps)
-    compare("c1d", sc, g, o, grads=("x", "v"), check_E=False)
+    compare("deform2d", sc, g, o, grads=("x", "v"), check_E=False)
     assert abs(o["gE"][0]) < 1e-15 and abs(g["gE"][0]) < 1e-6  # momentum conservation: dL/dE = 0
     w = random_seed(sc)
     g = gpu_run(sc, sc.steps, seed=w, knobs={"lanes": lanes})
     o = oracle_run(sc, sc.steps, seed=w)
-    compare(f"c1d random functional lanes={lanes}", sc, g, o, grads=("x", "v", "C", "F"))
+    compare(f"deform2d random functional lanes={lanes}", sc, g, o, grads=("x", "v", "C", "F"))
 
 
 @pytest.fixture(scope="module")
-def c3_oracle_64():
-    sc = scenes.c3().with_steps(64)
+def elastic3d_oracle_64():
+    sc = scenes.elastic3d().with_steps(64)
     return sc, oracle_run(sc, 64)
 
 
 @pytest.mark.parametrize("knobs", [dict(block=64), dict(block=128), dict(block=256), dict(block=128, lanes=4),
                                    dict(block=256, lanes=2), dict(block=64, lanes=2, rotate=0),
                                    dict(block=256, lanes=4, rotate=0), dict(block=128, lds=0, remap=1)])
-def test_c3_parity_64_steps(knobs, c3_oracle_64):
-    """3D workload c3 (64^3 grid, 32768 particles) gated at 64 steps, in each
+def test_elastic3d_parity_64_steps(knobs, elastic3d_oracle_64):
+    """3D workload elastic3d (64^3 grid, 32768 particles) gated at 64 steps, in each
     launch configuration."""
-    sc, o = c3_oracle_64
+    sc, o = elastic3d_oracle_64
     g = gpu_run(sc, 64, knobs=knobs)
-    compare(f"c3@64 {knobs}", sc, g, o, grads=("v", "x"), check_E=False)
+    compare(f"elastic3d@64 {knobs}", sc, g, o, grads=("v", "x"), check_E=False)
 
 
 def test_checkpointed_matches_oracle():
     """Checkpoint-recompute (K=4) over 20 steps on a deforming 2D body."""
-    sc = scenes.c1d().with_steps(20)
+    sc = scenes.deform2d().with_steps(20)
     w = random_seed(sc, 7)
     g = gpu_run(sc, 20, K=4, seed=w)
     o = oracle_run(sc, 20, K=4, seed=w)
-    compare("c1d@20 K=4", sc, g, o, grads=("x", "v", "C", "F"))
+    compare("deform2d@20 K=4", sc, g, o, grads=("x", "v", "C", "F"))
 
 
 @pytest.mark.parametrize("lanes", [1, 2, 4])
-def test_c5_batched_subset(lanes):
+def test_batched2d_batched_subset(lanes):
     """A few scenes of the batched workload run as one batch. The bodies start
     at rest, so until they reach the floor (about step 100) they fall rigidly
     with F = I and no stress: nothing depends on E before contact."""
-    full = scenes.c5(n_scenes=6, steps=64)
+    full = scenes.batched2d(n_scenes=6, steps=64)
     g = gpu_run(full, 64, knobs={"lanes": lanes})
     o = oracle_run(full, 64)
-    compare("c5[6]@64", full, g, o, grads=("v",), check_E=False)
+    compare("batched2d[6]@64", full, g, o, grads=("v",), check_E=False)
     assert np.abs(o["gE"]).max() < 1e-12 and np.abs(g["gE"]).max() < 1e-6
-    full = scenes.c5(n_scenes=6, steps=160)
+    full = scenes.batched2d(n_scenes=6, steps=160)
     w = random_seed(full, 5)
     g = gpu_run(full, 160, seed=w, knobs={"lanes": lanes})
     o = oracle_run(full, 160, seed=w)
-    compare("c5[6]@160 random functional", full, g, o, grads=("x", "v", "C", "F"))
+    compare("batched2d[6]@160 random functional", full, g, o, grads=("x", "v", "C", "F"))

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _case(dim, n_keep):
-    base = scenes.c1d() if dim == 2 else scenes.c3()
+    base = scenes.deform2d() if dim == 2 else scenes.elastic3d()
     if n_keep < base.n_particles:
         idx = np.sort(np.random.default_rng(1).choice(base.n_particles, n_keep, replace=False))
         base = base.subset([0])

@@ -1,10 +1,10 @@
 """Parity of the remaining workloads at their full sizes (GPU), in the launch
 configuration the benchmark uses, plus properties that hold at any size:
-  c2  2D actuated soft body, 512 steps: W, b gradients through the actuation;
-  c3  3D, full 256-step horizon;
-  c4  3D 128^3, 262144 particles: checkpointed tape vs oracle on a short
+  actuated2d  2D actuated soft body, 512 steps: W, b gradients through the actuation;
+  elastic3d  3D, full 256-step horizon;
+  elastic3d_long  3D 128^3, 262144 particles: checkpointed tape vs oracle on a short
       horizon, and K=64 vs full tape over all 1024 steps (GPU only);
-  c5  256 batched scenes, 256 steps: sampled scenes vs the oracle one by one,
+  batched2d  256 batched scenes, 256 steps: sampled scenes vs the oracle one by one,
       and batch vs per-scene runs of the same scenes on the GPU.
 """
 from dataclasses import replace
@@ -22,10 +22,10 @@ from parity import G_COS, G_REL, X_REL, act_table, compare, cos, gpu_run, log, o
 pytestmark = pytest.mark.gpu
 
 
-def test_c2_actuated_full():
-    sc = scenes.c2()
+def test_actuated2d_actuated_full():
+    sc = scenes.actuated2d()
     T = sc.steps
-    log(f"[c2] N={sc.n_particles} T={T}")
+    log(f"[actuated2d] N={sc.n_particles} T={T}")
     # Actuation signal on the GPU (mpm_actuation) vs the oracle's NumPy form.
     sim = rt.Simulator.for_scene(sc)
     W = torch.as_tensor(sc.act_W, device="cuda")
@@ -35,7 +35,7 @@ def test_c2_actuated_full():
     np.testing.assert_allclose(act_gpu.cpu().numpy(), act, atol=2e-6)
     g = gpu_run(sc, T, act=act_gpu.cpu().numpy(), sim=sim)
     o = oracle_run(sc, T, act=act)
-    compare("c2", sc, g, o, grads=("x", "v"))
+    compare("actuated2d", sc, g, o, grads=("x", "v"))
     # W, b gradients: GPU actuation adjoint of the GPU dL/da vs the oracle chain.
     gW = torch.zeros_like(W)
     gb = torch.zeros_like(b)
@@ -49,32 +49,32 @@ def test_c2_actuated_full():
 
 
 @pytest.mark.slow
-def test_c3_full_horizon():
-    sc = scenes.c3()
+def test_elastic3d_full_horizon():
+    sc = scenes.elastic3d()
     g = gpu_run(sc, sc.steps)
     o = oracle_run(sc, sc.steps)
     log(f"  oracle {o['seconds']:.1f} s")
-    compare("c3@256", sc, g, o, grads=("v", "x"), check_E=False)
+    compare("elastic3d@256", sc, g, o, grads=("v", "x"), check_E=False)
     w = random_seed(sc, 9)
     g = gpu_run(sc, sc.steps, seed=w)
     o = oracle_run(sc, sc.steps, seed=w)
-    compare("c3@256 random functional", sc, g, o, grads=("x", "v", "C", "F"))
+    compare("elastic3d@256 random functional", sc, g, o, grads=("x", "v", "C", "F"))
 
 
-def test_c4_full_size_short_horizon():
+def test_elastic3d_long_full_size_short_horizon():
     """All 262144 particles on the 128^3 grid, 8 steps with checkpoints every 2."""
-    sc = scenes.c4().with_steps(8, ckpt_every=2)
+    sc = scenes.elastic3d_long().with_steps(8, ckpt_every=2)
     w = random_seed(sc, 11)
     g = gpu_run(sc, 8, K=2, seed=w)
     o = oracle_run(sc, 8, K=2, seed=w)
     log(f"  oracle {o['seconds']:.1f} s")
-    compare("c4@8 K=2", sc, g, o, grads=("x", "v", "C", "F"))
+    compare("elastic3d_long@8 K=2", sc, g, o, grads=("x", "v", "C", "F"))
 
 
-def test_c4_checkpointed_equals_full_tape():
+def test_elastic3d_long_checkpointed_equals_full_tape():
     """Over the full 1024 steps (floor impact included), gradients of the
     checkpointed tape (K = 64) match the full tape's."""
-    sc = scenes.c4()
+    sc = scenes.elastic3d_long()
     T = sc.steps
     sim = rt.Simulator.for_scene(sc)
     a = gpu_run(sc, T, K=64, sim=sim)
@@ -82,7 +82,7 @@ def test_c4_checkpointed_equals_full_tape():
     assert a["flags"] == 0 and b["flags"] == 0
     xr = rel(a["final"][0], b["final"][0])
     r = {k: (cos(a["g0"][i], b["g0"][i]), rel(a["g0"][i], b["g0"][i])) for i, k in enumerate("xvCF")}
-    log(f"[c4 K=64 vs full] x rel {xr:.3g}; grads {r}; dL/dE {a['gE'][0]:.6g} vs {b['gE'][0]:.6g}")
+    log(f"[elastic3d_long K=64 vs full] x rel {xr:.3g}; grads {r}; dL/dE {a['gE'][0]:.6g} vs {b['gE'][0]:.6g}")
     assert xr < 1e-6
     for k in "xv":
         assert r[k][0] >= G_COS and r[k][1] <= G_REL, (k, r[k])
@@ -91,10 +91,10 @@ def test_c4_checkpointed_equals_full_tape():
     assert abs(b["gE"][0]) > 1e-9
 
 
-def test_c5_batched_full_sampled():
+def test_batched2d_batched_full_sampled():
     """All 256 scenes in one batch for 256 steps; 3 sampled scenes against the
     oracle run one by one (scenes are independent)."""
-    sc = scenes.c5()
+    sc = scenes.batched2d()
     w = random_seed(sc, 13)
     g = gpu_run(sc, sc.steps, seed=w)
     assert g["flags"] == 0
@@ -104,12 +104,12 @@ def test_c5_batched_full_sampled():
         o = oracle_run(one, sc.steps, seed=w[lo:hi])
         gk = {"final": tuple(a[lo:hi] for a in g["final"]), "g0": tuple(a[lo:hi] for a in g["g0"]),
               "gE": g["gE"][k:k + 1], "flags": g["flags"]}
-        compare(f"c5 scene {k} (N={hi - lo})", one, gk, o, grads=("x", "v", "C", "F"))
+        compare(f"batched2d scene {k} (N={hi - lo})", one, gk, o, grads=("x", "v", "C", "F"))
 
 
-def test_c5_batch_equals_per_scene_gpu():
+def test_batched2d_batch_equals_per_scene_gpu():
     """The batched launch and per-scene launches give the same trajectories."""
-    sc = scenes.c5(n_scenes=16, steps=64)
+    sc = scenes.batched2d(n_scenes=16, steps=64)
     g = gpu_run(sc, 64)
     for k in (0, 7, 15):
         one = sc.subset([k])
@@ -122,7 +122,7 @@ def test_c5_batch_equals_per_scene_gpu():
 def test_error_flags():
     """Out-of-grid, inverted and non-finite particles raise their flags; the
     kernels skip them (no out-of-bounds access) and the call completes."""
-    base = scenes.c1()
+    base = scenes.translate2d()
     cases = []
     x = base.x.copy()
     x[5] = [0.003, 0.5]  # x/dx - 1/2 < 0: the stencil would leave the grid
@@ -149,7 +149,7 @@ def test_error_flags():
 
 def test_autograd_trajectory_matches_tape_api():
     """MPMTrajectory.apply + torch loss + backward equals the tape calls."""
-    sc = scenes.c1d().with_steps(32)
+    sc = scenes.deform2d().with_steps(32)
     sim = rt.Simulator.for_scene(sc)
     p = rt.params_for_scene(sc)
     init = rt.state_for_scene(sc)
@@ -178,7 +178,7 @@ def test_autograd_trajectory_matches_tape_api():
 
 
 def test_tape_misuse():
-    sc = scenes.c1()
+    sc = scenes.translate2d()
     sim = rt.Simulator.for_scene(sc)
     p = rt.params_for_scene(sc)
     tape = sim.tape(4)

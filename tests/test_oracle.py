@@ -143,7 +143,7 @@ def test_stress_frame_indifference():
 def test_mass_and_momentum(dim):
     """Grid mass equals particle mass; with no stencil touching a sticky node,
     sum m v changes by exactly M g dt per step."""
-    sc = scenes.fd8(dim) if dim == 3 else scenes.random_state(scenes.c1(), seed=3)
+    sc = scenes.fd8(dim) if dim == 3 else scenes.random_state(scenes.translate2d(), seed=3)
     st = _state(sc)
     gp, gv, err = orc.grid(sc, st)
     assert err == 0
@@ -160,11 +160,11 @@ def test_mass_and_momentum(dim):
     np.testing.assert_allclose(dp, expect, rtol=1e-11, atol=1e-15)
 
 
-def test_c1_closed_form():
-    """Workload c1 is a rigid translation: golden shift, C = 0, F = I, and the
+def test_translate2d_closed_form():
+    """Workload translate2d is a rigid translation: golden shift, C = 0, F = I, and the
     gradients dL/dv0 = (T dt, 0), dL/dE = 0."""
-    g = {r[0]: float(r[1]) for r in _golden_rows("c1_closed_form.txt")}
-    sc = scenes.c1()
+    g = {r[0]: float(r[1]) for r in _golden_rows("translate2d_closed_form.txt")}
+    sc = scenes.translate2d()
     st = _state(sc)
     sT, _, err = orc.run_fwd(sc, sc.steps, st)
     assert err == 0
@@ -289,7 +289,7 @@ def test_checkpoint_equivalence():
 def test_batch_independence():
     """Scene j of a batch gives bitwise the same outputs and gradients alone, and
     other scenes' E gradients are unaffected by it."""
-    full = scenes.c5(n_scenes=3, steps=8)
+    full = scenes.batched2d(n_scenes=3, steps=8)
     st = _state(full)
     out, _, err = orc.run_fwd(full, 8, st)
     assert err == 0
@@ -307,7 +307,7 @@ def test_batch_independence():
 
 
 def _small_actuated(n_keep=300, steps=16):
-    sc = scenes.c2()
+    sc = scenes.actuated2d()
     keep = np.random.default_rng(0).choice(sc.n_particles, n_keep, replace=False)
     keep.sort()
     return replace(sc, steps=steps, offsets=np.array([0, n_keep], np.int32), x=sc.x[keep], v=sc.v[keep],
