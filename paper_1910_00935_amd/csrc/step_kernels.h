@@ -964,23 +964,39 @@ __device__ __forceinline__ void g2p_body(const StepConsts& k, const Sten<D>& st,
   }
 }
 
+// An affine field over the stencil, a_c + sum_b M_cb (x_i - x_p)_b, kept as
+// per-axis terms: t[b][c][o] = M_cb dl_b[o] (+ a_c on axis 0), so a visited
+// node costs D - 1 adds per component instead of D multiply-adds (the terms
+// of the outer axes are shared by the inner loop's nodes).
+template <int D>
+struct AffineTab {
+  float t[D][D][3];
+  __device__ __forceinline__ AffineTab(const Sten<D>& st, const float (&a)[D], const float (&M)[D][D]) {
+#pragma unroll
+    for (int b = 0; b < D; ++b)
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int o = 0; o < 3; ++o) t[b][c][o] = (b == 0) ? fmaf(M[c][b], st.dl[b][o], a[c]) : M[c][b] * st.dl[b][o];
+  }
+  __device__ __forceinline__ float at(int c, int o0, int o1, int o2) const {
+    float v = t[0][c][o0] + t[1][c][o1];
+    if constexpr (D == 3) v += t[2][c][o2];
+    return v;
+  }
+};
+
 // p2g: scatter m and P of one particle (A and m v precomputed).
 template <int D, int S0, class SA>
 __device__ __forceinline__ void p2g_body(const StepConsts& k, const Sten<D>& st, float mass, const float (&mv)[D],
                                          const float (&A)[D][D], const SA& g) {
+  const AffineTab<D> mom(st, mv, A);  // m v + A (x_i - x_p)
   for_nodes<D, S0>(st, [&](int o0, int o1, int o2) {
     const float w = wgt<D>(st, o0, o1, o2);
-    float dl[D];
-    delta<D>(st, o0, o1, o2, k.dx, dl);
     const int q = g.idx(st, o0, o1, o2);
     g.add(q, 0, w * mass);
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      float Ad = 0.0f;
-#pragma unroll
-      for (int b = 0; b < D; ++b) Ad += A[a][b] * dl[b];
-      g.add(q, 1 + a, w * (mv[a] + Ad));
-    }
+    for (int a = 0; a < D; ++a) g.add(q, 1 + a, w * mom.at(a, o0, o1, o2));
   });
 }
 
@@ -1095,6 +1111,7 @@ __device__ __forceinline__ void p2g_adj_body(const StepConsts& k, const Sten<D>&
                                              const float (&A)[D][D], const Nodes<D, L>& g, const Nodes<D, L>& ad,
                                              float (&gx)[D], float (&vb)[D], float (&Abar)[D][D]) {
   float gxa[D] = {};
+  const AffineTab<D> mom(st, mv, A);  // m v + A (x_i - x_p)
   for_nodes<D, S0>(st, [&](int o0, int o1, int o2) {
     float Pb[D], mb;
     node_adj<D>(k, st, o0, o1, o2, g, ad, Pb, mb);
@@ -1105,10 +1122,7 @@ __device__ __forceinline__ void p2g_adj_body(const StepConsts& k, const Sten<D>&
     float contrib = mass * mb;
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      float Ad = 0.0f;
-#pragma unroll
-      for (int b = 0; b < D; ++b) Ad += A[c][b] * dl[b];
-      contrib += Pb[c] * (mv[c] + Ad);
+      contrib += Pb[c] * mom.at(c, o0, o1, o2);
       vb[c] += w * Pb[c];
 #pragma unroll
       for (int b = 0; b < D; ++b) Abar[c][b] += w * Pb[c] * dl[b];
@@ -1158,21 +1172,18 @@ __device__ __forceinline__ void g2p_adj_body(const StepConsts& k, const Sten<D>&
                                              const float (&Bm)[D][D], const GA& g, const SA& ad, float (&px)[D],
                                              bool scatter) {
   float pxa[D] = {};
+  const AffineTab<D> rt(st, vt, Bm);  // r = v~ + B (x_i - x_p)
   for_nodes<D, S0>(st, [&](int o0, int o1, int o2) {
     float v[D];
     node_vel<D>(k, st, o0, o1, o2, g, v);
     const float w = wgt<D>(st, o0, o1, o2);
-    float dw[D], dl[D];
+    float dw[D];
     dwgt<D>(st, o0, o1, o2, k.inv_dx, dw);
-    delta<D>(st, o0, o1, o2, k.dx, dl);
     float r[D], vr = 0.0f;
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      float s = vt[c];
-#pragma unroll
-      for (int b = 0; b < D; ++b) s += Bm[c][b] * dl[b];
-      r[c] = s;
-      vr += v[c] * s;
+      r[c] = rt.at(c, o0, o1, o2);
+      vr += v[c] * r[c];
     }
     if (scatter) {
       const int q = ad.idx(st, o0, o1, o2);
