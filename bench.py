@@ -216,7 +216,47 @@ def run_cpu_baseline(sample_steps):
     dt = time.perf_counter() - t0
     return {"value": sc.n_particles * sample_steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"3D 64^3 workload, all {sc.n_particles} particles, first {sample_steps} of 256 steps, "
-                      f"fwd + reverse, {dt:.1f} s"}
+                      f"fwd + reverse, {dt:.1f} s", "host": _host()}
+
+
+def _host():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu": model}
+
+
+def run_cpu_baseline_batched(sample_steps, workers):
+    """The FP64 oracle on the batched 2D workload with every host core busy:
+    the 256 scenes run as independent oracle calls on `workers` threads (the
+    oracle is a C library called through ctypes, which releases the GIL),
+    first `sample_steps` steps, forward then reverse."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle as orc
+    from paper_1910_00935_amd import scenes
+    sc = scenes.batched2d()
+    parts = [sc.subset([k]) for k in range(sc.n_scenes)]
+
+    def one(s):
+        st = orc.pack(s.x, s.v, s.C, s.F)
+        sT, _, _ = orc.run_fwd(s, sample_steps, st)
+        _, seed = orc.loss_mean_pos(s, sT, s.loss_axis, s.loss_sign)
+        orc.run_bwd(s, sample_steps, sample_steps, st, seed)
+        return s.n_particles
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        n = sum(ex.map(one, parts))
+    dt = time.perf_counter() - t0
+    return {"value": n * sample_steps / dt, "unit": "particle-steps/s", "cores": workers, "kind": "oracle",
+            "sample": f"batched 2D workload, all {sc.n_scenes} scenes ({n} particles), first {sample_steps} of "
+                      f"{sc.steps} steps, fwd + reverse, one oracle call per scene on {workers} threads, {dt:.1f} s"}
 
 
 def run_batched(args, torch, rt, scenes, n_scenes=256, steps=256):
@@ -276,6 +316,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample-steps", type=int, default=128)
+    ap.add_argument("--cpu-batched-steps", type=int, default=32)
+    ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default launch configuration")
@@ -348,6 +390,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", flush=True)
         out["cpu_baseline"] = run_cpu_baseline(args.cpu_sample_steps)
+        out["cpu_baseline_batched_all_cores"] = run_cpu_baseline_batched(args.cpu_batched_steps, args.cpu_workers)
     print(json.dumps(out), flush=True)
 
 
