@@ -309,17 +309,23 @@ struct SpanGuard {
 };
 
 template <int D, int LPP>
-mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& a, hipStream_t st) {
+mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& args, hipStream_t st) {
   span_step(c, 0, st);
+  FwdArgs a = args;
+  a.k.threads = c.block;
+  a.k.groups = c.n_blocks;
   hipLaunchKernelGGL((mpm::k_fwd<D, LPP>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
   LAUNCH_TRY();
   return MPM_OK;
 }
 
 template <int D, int LPP>
-mpm_status launch_bwd(const mpm_ctx& c, const BwdArgs& a, hipStream_t st) {
+mpm_status launch_bwd(const mpm_ctx& c, const BwdArgs& args, hipStream_t st) {
   span_step(c, 1, st);
-  const int nb = c.n_blocks * (a.split_c ? 2 : 1);
+  const int nb = c.n_blocks * (args.split_c ? 2 : 1);
+  BwdArgs a = args;
+  a.k.threads = c.block;
+  a.k.groups = nb;
   hipLaunchKernelGGL((mpm::k_bwd<D, LPP>), dim3(nb), dim3(c.block), 0, st, a);
   LAUNCH_TRY();
   return MPM_OK;

@@ -57,6 +57,8 @@ struct StepConsts {
   const int4* blocks;   // [n_blocks] scene-aligned workgroups (first, count, scene); required with
                         // several scenes, null with one
   int n_blocks;         // workgroups per particle pass
+  int threads;          // threads per workgroup of this launch (blockDim.x, kept in a scalar register)
+  int groups;           // workgroups of this launch (gridDim.x)
   const float* E;
   const float* nu;
   const float* vol;
@@ -208,10 +210,10 @@ __device__ __forceinline__ bool node_active(const Sten<D>& st, int o0, int o1, i
   return in && m > 0.0f;
 }
 
-__device__ __forceinline__ void zero_range(float4* p, long n) {
+__device__ __forceinline__ void zero_range(float4* p, long n, int threads, int groups) {
   if (!p) return;
-  const long stride = long(gridDim.x) * blockDim.x;
-  for (long q = long(blockIdx.x) * blockDim.x + threadIdx.x; q < n; q += stride) p[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+  const long stride = long(groups) * threads;
+  for (long q = long(blockIdx.x) * threads + threadIdx.x; q < n; q += stride) p[q] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // Read of a value that is uniform over the workgroup and was written by an
@@ -239,7 +241,8 @@ __device__ __forceinline__ int div_small(int r, int d, float rcp, int& rem) {
 // launch that later clears that grid zeroes the recorded boxes instead of the
 // whole grid; boxes are clamped to the grid.
 template <int D>
-__device__ __forceinline__ void clear_box_nodes(float4* grid, int4 lo, int4 ex, int n, int nodes, int n_scenes) {
+__device__ __forceinline__ void clear_box_nodes(float4* grid, int4 lo, int4 ex, int n, int nodes, int n_scenes,
+                                                int threads) {
   const int l0 = max(lo.x, 0), l1 = max(lo.y, 0), l2 = (D == 3) ? max(lo.z, 0) : 0;
   const int e0 = min(lo.x + ex.x, n) - l0, e1 = min(lo.y + ex.y, n) - l1;
   const int e2 = (D == 3) ? min(lo.z + ex.z, n) - l2 : 1;
@@ -252,7 +255,7 @@ __device__ __forceinline__ void clear_box_nodes(float4* grid, int4 lo, int4 ex, 
   const int s1 = (lo.w >= 0) ? min(lo.w + 1, n_scenes) : n_scenes;
   for (int sc = s0; sc < s1; ++sc) {
     float4* g = grid + long(sc) * nodes;
-    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    for (int q = threadIdx.x; q < total; q += threads) {
       int c0, c1, c2, r;
       if (small) {
         r = div_small(q, e2, r2, c2);
@@ -299,13 +302,13 @@ __device__ __forceinline__ void clear_entry(const ClearSpec& s0, const ClearSpec
   ex = load_uniform(t + 2 * jj + 1);
 }
 
-__device__ __forceinline__ ClearJobs clear_jobs_fetch(const ClearSpec& s0, const ClearSpec& s1) {
+__device__ __forceinline__ ClearJobs clear_jobs_fetch(const ClearSpec& s0, const ClearSpec& s1, int groups) {
   ClearJobs c;
   c.n = 0;
   const int m = clear_entries(s0) + clear_entries(s1);
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
-    const int j = int(blockIdx.x) + r * int(gridDim.x);
+    const int j = int(blockIdx.x) + r * groups;
     if (j < m) {
       clear_entry(s0, s1, j, c.lo[r], c.ex[r], c.which[r]);
       c.n = r + 1;
@@ -315,20 +318,21 @@ __device__ __forceinline__ ClearJobs clear_jobs_fetch(const ClearSpec& s0, const
 }
 
 template <int D>
-__device__ __forceinline__ void clear_jobs_run(const ClearJobs& c, const ClearSpec& s0, const ClearSpec& s1, int n,
-                                               int nodes, int n_scenes) {
+__device__ __forceinline__ void clear_jobs_run(const ClearJobs& c, const ClearSpec& s0, const ClearSpec& s1,
+                                               const StepConsts& k) {
 #pragma unroll
   for (int r = 0; r < 2; ++r)
-    if (r < c.n) clear_box_nodes<D>(c.which[r] == 0 ? s0.g : s1.g, c.lo[r], c.ex[r], n, nodes, n_scenes);
+    if (r < c.n)
+      clear_box_nodes<D>(c.which[r] == 0 ? s0.g : s1.g, c.lo[r], c.ex[r], k.n, k.nodes, k.n_scenes, k.threads);
   const int m = clear_entries(s0) + clear_entries(s1);
-  for (int j = int(blockIdx.x) + 2 * int(gridDim.x); j < m; j += int(gridDim.x)) {
+  for (int j = int(blockIdx.x) + 2 * k.groups; j < m; j += k.groups) {
     int4 lo, ex;
     int which;
     clear_entry(s0, s1, j, lo, ex, which);
-    clear_box_nodes<D>(which == 0 ? s0.g : s1.g, lo, ex, n, nodes, n_scenes);
+    clear_box_nodes<D>(which == 0 ? s0.g : s1.g, lo, ex, k.n, k.nodes, k.n_scenes, k.threads);
   }
-  if (s0.g && !s0.box) zero_range(s0.g, s0.dense_n);
-  if (s1.g && !s1.box) zero_range(s1.g, s1.dense_n);
+  if (s0.g && !s0.box) zero_range(s0.g, s0.dense_n, k.threads, k.groups);
+  if (s1.g && !s1.box) zero_range(s1.g, s1.dense_n, k.threads, k.groups);
 }
 
 __device__ __forceinline__ void atomic_add_f32(float* p, float v) { unsafeAtomicAdd(p, v); }
@@ -569,6 +573,7 @@ __device__ __forceinline__ int fixed_exponent(float bmax) {
 struct BlockRed {
   int* sh;
   int phase;
+  int nw;  // waves per workgroup
 };
 
 template <int D>
@@ -599,7 +604,7 @@ __device__ Box<D> block_reduce(bool valid, const int (&base)[D], float bound, Bl
     b = max(b, __shfl_xor(b, off, 64));
   }
   int* s = r.sh + (r.phase & 1) * 32;
-  const int w = int(threadIdx.x >> 6), nw = int((blockDim.x + 63) >> 6);
+  const int w = int(threadIdx.x >> 6), nw = r.nw;
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -777,18 +782,6 @@ __device__ __forceinline__ int tile_global_index(const Tile<D>& T, int q, int n)
   return g;
 }
 
-// Loads the first NC components of the box's nodes into a SoA tile.
-template <int D, int NC>
-__device__ __forceinline__ void tile_load(const Tile<D>& T, const float4* g, int n, float* tile) {
-  for (int q = threadIdx.x; q < T.n; q += blockDim.x) {
-    const float4 v = g[tile_global_index<D>(T, q, n)];
-    tile[q] = v.x;
-    if (NC > 1) tile[kTileMax + q] = v.y;
-    if (NC > 2) tile[2 * kTileMax + q] = v.z;
-    if (NC > 3) tile[3 * kTileMax + q] = v.w;
-  }
-}
-
 // Scene-grid coordinates of tile node q; returns its linear index.
 template <int D>
 __device__ __forceinline__ int tile_node(const Tile<D>& T, int q, int n, int (&c)[D]) {
@@ -814,43 +807,11 @@ __device__ __forceinline__ bool tile_node_interior(const int (&c)[D], int n, int
   return in;
 }
 
-template <int D, int NC>
-__device__ __forceinline__ void tile_zero(const Tile<D>& T, float* tile) {
-  for (int q = threadIdx.x; q < T.n; q += blockDim.x)
-#pragma unroll
-    for (int c = 0; c < NC; ++c) tile[c * kTileMax + q] = 0.0f;
-}
-
-// Adds the non-zero nodes of the tile (first NC components) into the global grid.
-template <int D, int NC>
-__device__ __forceinline__ void tile_flush(const Tile<D>& T, const float* tile, float4* g, int n) {
-  for (int q = threadIdx.x; q < T.n; q += blockDim.x) {
-    float v[NC];
-    bool nz = false;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      v[c] = tile[c * kTileMax + q];
-      nz = nz || (v[c] != 0.0f);
-    }
-    if (nz) {
-      float* dst = reinterpret_cast<float*>(g + tile_global_index<D>(T, q, n));
-#pragma unroll
-      for (int c = 0; c < NC; ++c) atomic_add_f32(dst + c, v[c]);
-    }
-  }
-}
-
-template <int D, int NC>
-__device__ __forceinline__ void tile_zero64(const Tile<D>& T, long long* tile) {
-  for (int q = threadIdx.x; q < T.n; q += blockDim.x)
-#pragma unroll
-    for (int c = 0; c < NC; ++c) tile[c * kTileMax + q] = 0;
-}
-
 // Adds the non-zero nodes of a fixed-point tile into the global grid.
 template <int D, int NC>
-__device__ __forceinline__ void tile_flush64(const Tile<D>& T, const long long* tile, float4* g, int n) {
-  for (int q = threadIdx.x; q < T.n; q += blockDim.x) {
+__device__ __forceinline__ void tile_flush64(const Tile<D>& T, const long long* tile, float4* g, int n,
+                                             int threads) {
+  for (int q = threadIdx.x; q < T.n; q += threads) {
     long long v[NC];
     bool nz = false;
 #pragma unroll
@@ -1048,17 +1009,17 @@ constexpr int kTileBatch = 4;
 // (components 0..D-1 = v), so gathers read v instead of forming P / m per visit.
 template <int D>
 __device__ __forceinline__ void tile_load_vel(const StepConsts& k, const Tile<D>& T, const float4* g, float* tile) {
-  for (int q0 = threadIdx.x; q0 < T.n; q0 += kTileBatch * blockDim.x) {
+  for (int q0 = threadIdx.x; q0 < T.n; q0 += kTileBatch * k.threads) {
     float4 gm[kTileBatch];
 #pragma unroll
     for (int r = 0; r < kTileBatch; ++r) {
-      const int q = q0 + r * int(blockDim.x);
+      const int q = q0 + r * k.threads;
       int c[D];
       if (q < T.n) gm[r] = g[tile_node<D>(T, q, k.n, c)];
     }
 #pragma unroll
     for (int r = 0; r < kTileBatch; ++r) {
-      const int q = q0 + r * int(blockDim.x);
+      const int q = q0 + r * k.threads;
       if (q < T.n) {
         int c[D];
         tile_node<D>(T, q, k.n, c);
@@ -1076,11 +1037,11 @@ __device__ __forceinline__ void tile_load_vel(const StepConsts& k, const Tile<D>
 template <int D>
 __device__ __forceinline__ void tile_load_adj(const StepConsts& k, const Tile<D>& T, const float4* g,
                                               const float4* ad, float* tile) {
-  for (int q0 = threadIdx.x; q0 < T.n; q0 += kTileBatch * blockDim.x) {
+  for (int q0 = threadIdx.x; q0 < T.n; q0 += kTileBatch * k.threads) {
     float4 gm[kTileBatch], vb4[kTileBatch];
 #pragma unroll
     for (int r = 0; r < kTileBatch; ++r) {
-      const int q = q0 + r * int(blockDim.x);
+      const int q = q0 + r * k.threads;
       int c[D];
       if (q < T.n) {
         const int gi = tile_node<D>(T, q, k.n, c);
@@ -1090,7 +1051,7 @@ __device__ __forceinline__ void tile_load_adj(const StepConsts& k, const Tile<D>
     }
 #pragma unroll
     for (int r = 0; r < kTileBatch; ++r) {
-      const int q = q0 + r * int(blockDim.x);
+      const int q = q0 + r * k.threads;
       if (q < T.n) {
         int c[D];
         tile_node<D>(T, q, k.n, c);
@@ -1248,15 +1209,15 @@ __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i,
   }
   if (T.on) {
     __syncthreads();
-    tile_flush64<D, D + 1>(T, tile, g, k.n);
+    tile_flush64<D, D + 1>(T, tile, g, k.n, k.threads);
   }
 }
 
 // Zeroes the first NC components of a whole fixed-point tile (no barrier: the
 // next block reduction's barrier orders it before the scatter).
 template <int NC>
-__device__ __forceinline__ void zero_tile64(long long* tile) {
-  for (int q = threadIdx.x; q < NC * kTileMax; q += blockDim.x) tile[q] = 0;
+__device__ __forceinline__ void zero_tile64(long long* tile, int threads) {
+  for (int q = threadIdx.x; q < NC * kTileMax; q += threads) tile[q] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1277,7 +1238,7 @@ struct LaneMap {
   int first, i, sub, count, scene;
   bool live, owner;
   __device__ __forceinline__ LaneMap(const StepConsts& k, int block_index) {
-    const int per_block = int(blockDim.x) / LPP;
+    const int per_block = k.threads / LPP;
     int end;
     if (k.blocks) {
       const int4 bi = load_uniform(k.blocks + block_index);
@@ -1299,7 +1260,7 @@ struct LaneMap {
       i = first + int(threadIdx.x >> 1);
     } else {
       sub = 0;
-      i = first + lane_particle(threadIdx.x, blockDim.x, k.remap);
+      i = first + lane_particle(threadIdx.x, k.threads, k.remap);
     }
     live = i < end;
     owner = sub == 0;
@@ -1312,8 +1273,8 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   __shared__ long long tile64[(D + 1) * kTileMax];  // P2G scatter tile (fixed point)
   __shared__ float vtile[D * kTileMax];              // G2P velocity tile
   __shared__ int red[64];
-  BlockRed rd{red, 0};
   const StepConsts& k = a.k;
+  BlockRed rd{red, 0, (k.threads + 63) >> 6};
   const LaneMap<LPP> lm(k, int(blockIdx.x));
   const int i = lm.i, sub = lm.sub;
   const bool live = lm.live;
@@ -1328,8 +1289,8 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   PState<D> p;
   if (live) load_state<D>(a.in, i, p);
   const ClearSpec c0{a.clear, a.clear_box, a.clear_nbox, a.clear_n}, c1{nullptr, nullptr, 0, 0};
-  const ClearJobs cj = clear_jobs_fetch(c0, c1);
-  if (a.do_p2g && k.lds) zero_tile64<D + 1>(tile64);
+  const ClearJobs cj = clear_jobs_fetch(c0, c1, k.groups);
+  if (a.do_p2g && k.lds) zero_tile64<D + 1>(tile64, k.threads);
   Tile<D> T = empty_tile<D>();
   const float4* g = a.grid_in + long(sc) * k.nodes;
   if (a.do_g2p && a.box_in) {
@@ -1345,7 +1306,7 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
       if (T.on) tile_load_vel<D>(k, T, g, vtile);
     }
     if (T.on) __syncthreads();
-    clear_jobs_run<D>(cj, c0, c1, k.n, k.nodes, k.n_scenes);
+    clear_jobs_run<D>(cj, c0, c1, k);
     if (ok) {
       if (T.on && in_tile<D>(T, st.base))
         g2p_body<D, true, S0>(k, st, lds_nodes<D>(vtile, T), p);
@@ -1356,7 +1317,7 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
     }
     if (live && lm.owner) store_state<D>(a.out, i, p);
   } else {
-    clear_jobs_run<D>(cj, c0, c1, k.n, k.nodes, k.n_scenes);
+    clear_jobs_run<D>(cj, c0, c1, k);
   }
   if (a.do_p2g)
     p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_row, a.grid_out, tile64, rd, err, a.box_out,
@@ -1386,8 +1347,8 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   __shared__ float tV[D * kTileMax];            // phase B: velocity tile
   __shared__ long long tS[(D + 1) * kTileMax];  // scatter tile: phase B (adjoint grid), phase C (grid)
   __shared__ int red[64];
-  BlockRed rd{red, 0};
   const StepConsts& k = a.k;
+  BlockRed rd{red, 0, (k.threads + 63) >> 6};
   // With split_c, workgroups [0, nb) run phases A and B and workgroups
   // [nb, 2 nb) run phase C on the same particles: C does not depend on A or B.
   const int nb = k.n_blocks;
@@ -1402,12 +1363,12 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   unsigned err = 0;
   const ClearSpec c0{a.clear0, a.clear0_box, a.clear0_nbox, a.clear0_n};
   const ClearSpec c1{a.clear1, a.clear1_box, a.clear1_nbox, a.clear1_n};
-  const ClearJobs cj = clear_jobs_fetch(c0, c1);
+  const ClearJobs cj = clear_jobs_fetch(c0, c1, k.groups);
   if (role_c) {
-    if (k.lds) zero_tile64<D + 1>(tS);
+    if (k.lds) zero_tile64<D + 1>(tS, k.threads);
     PState<D> p;
     if (live) load_state<D>(a.stC, i, p);
-    clear_jobs_run<D>(cj, c0, c1, k.n, k.nodes, k.n_scenes);
+    clear_jobs_run<D>(cj, c0, c1, k);
     p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
     if (err) atomicOr(k.err, err);
     return;
@@ -1454,16 +1415,12 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
         for (int b = 0; b < D; ++b) CnB[c][b] = a.cnext[(c * D + b) * a.cnext_stride + i];
     }
   }
-  if (!a.final_out && k.lds) zero_tile64<D>(tS);
+  if (!a.final_out && k.lds) zero_tile64<D>(tS, k.threads);
   Tile<D> TA = empty_tile<D>(), TB = empty_tile<D>();
-  if (a.a_mode == 1 && a.boxA_in) {
-    TA = recorded_tile<D>(a.boxA_in, wg, sc, one_scene, k.lds, k.n);
-    if (TA.on) tile_load_adj<D>(k, TA, a.gA + long(sc) * k.nodes, a.aA + long(sc) * k.nodes, tA);
-  }
-  if (!a.final_out && a.boxB_in) {
-    TB = recorded_tile<D>(a.boxB_in, wg, sc, one_scene, k.lds, k.n);
-    if (TB.on) tile_load_vel<D>(k, TB, a.gB + long(sc) * k.nodes, tV);
-  }
+  if (a.a_mode == 1 && a.boxA_in) TA = recorded_tile<D>(a.boxA_in, wg, sc, one_scene, k.lds, k.n);
+  if (!a.final_out && a.boxB_in) TB = recorded_tile<D>(a.boxB_in, wg, sc, one_scene, k.lds, k.n);
+  if (TA.on) tile_load_adj<D>(k, TA, a.gA + long(sc) * k.nodes, a.aA + long(sc) * k.nodes, tA);
+  if (TB.on) tile_load_vel<D>(k, TB, a.gB + long(sc) * k.nodes, tV);
 
   // dL/dstate(s+1): gx, gv, gC, gF.
   double eb = 0.0, actb = 0.0;
@@ -1538,7 +1495,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   }
 
   if (a.final_out) {
-    clear_jobs_run<D>(cj, c0, c1, k.n, k.nodes, k.n_scenes);
+    clear_jobs_run<D>(cj, c0, c1, k);
     if (!live || !owner) return;
     const int o = a.out_perm ? a.out_perm[i] : i;
     const int os = a.out.stride;
@@ -1580,7 +1537,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
       if (T.on) tile_load_vel<D>(k, T, g, tV);
     }
     if (T.on) __syncthreads();
-    clear_jobs_run<D>(cj, c0, c1, k.n, k.nodes, k.n_scenes);
+    clear_jobs_run<D>(cj, c0, c1, k);
     const bool in_t = T.on && ok && in_tile<D>(T, st.base);
     float Bm[D][D] = {}, vt[D] = {}, bound = 0.0f;
     if (ok) {
@@ -1652,7 +1609,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
       Tile<D> TS = T;
       TS.e = e_fix;
       __syncthreads();
-      tile_flush64<D, D>(TS, tS, ad, k.n);
+      tile_flush64<D, D>(TS, tS, ad, k.n, k.threads);
     }
     if (live && owner) {
 #pragma unroll
@@ -1669,7 +1626,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     PState<D> p;
     if (live) load_state<D>(a.stC, i, p);
     __syncthreads();  // every thread is done with the scatter tile of phase B
-    if (k.lds) zero_tile64<D + 1>(tS);
+    if (k.lds) zero_tile64<D + 1>(tS, k.threads);
     p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
   }
   if (err) atomicOr(k.err, err);
