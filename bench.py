@@ -316,7 +316,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample-steps", type=int, default=128)
-    ap.add_argument("--cpu-batched-steps", type=int, default=32)
+    ap.add_argument("--cpu-batched-steps", type=int, default=256)
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
