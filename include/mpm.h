@@ -145,7 +145,7 @@ size_t mpm_workspace_bytes(const mpm_ctx* ctx);
 mpm_status mpm_bind_workspace(mpm_ctx* ctx, void* dev, size_t bytes);
 
 /* Sets a knob: "block" (threads per workgroup of the per-particle kernels:
- * 64, 128 or 256); "lds" (0/1, default 1: stage each workgroup's stencil
+ * 64, 128, 192 or 256); "lds" (0/1, default 1: stage each workgroup's stencil
  * footprint in LDS when it fits, else use global memory directly); "split"
  * (0/1, default 1: run the reverse launch's grid recompute for the previous
  * step in workgroups of its own, beside the adjoint workgroups); "remap"

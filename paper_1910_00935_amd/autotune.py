@@ -27,7 +27,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mpm_autotune.js
 
 # Candidate grid; the first entry is the library default.
 SPACE = {
-    "block": (128, 64, 256),
+    "block": (128, 64, 192, 256),
     "lanes": (1, 2, 4),
     "rotate": (1, 0),
     "lds": (1,),

@@ -621,7 +621,7 @@ mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value) {
   if (!ctx || !key) return MPM_E_ARG;
   const std::string k(key);
   if (k == "block") {
-    if (value != 64 && value != 128 && value != 256) return MPM_E_ARG;
+    if (value != 64 && value != 128 && value != 192 && value != 256) return MPM_E_ARG;
     ctx->block = int(value);
     return update_blocks(*ctx);
   }

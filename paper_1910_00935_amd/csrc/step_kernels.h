@@ -18,7 +18,7 @@
 //
 // LDS staging: particles are sorted by cell (Morton order), so the stencils of
 // one workgroup cover a small box of nodes. Each phase computes that box
-// (block-wide min/max of the stencil bases); when it fits kTileMax nodes and
+// (block-wide min/max of the stencil bases); when it fits kTileCap<D> nodes and
 // the workgroup holds one scene, gathers read the box once into LDS and
 // scatters accumulate in LDS and flush each non-zero node to HBM with one
 // hardware FP32 atomic per component. Otherwise the phase reads and scatters
@@ -41,7 +41,13 @@
 
 namespace mpm {
 
-constexpr int kTileMax = 512;  // nodes per LDS tile (float4 each)
+// Nodes per LDS tile: 512 in 3D, 768 in 2D. A workgroup whose box exceeds it
+// falls back to global atomics, which costs far more than the LDS it would
+// have used: in the batched 2D workload at 256 particles per workgroup about
+// 5 % of the boxes exceed 512 nodes and under 1 % exceed 768, and 768 still
+// leaves the kernels' LDS use balanced with their register use.
+template <int D>
+constexpr int kTileCap = (D == 3) ? 512 : 768;
 
 struct StepConsts {
   int N;          // particles
@@ -430,7 +436,7 @@ struct Tile {
 
 // Node addressing: a box of the scene's grid staged in LDS (L = true), or the
 // scene's global grid. LDS tiles are structure-of-arrays, component c of tile
-// node q at tile[c * kTileMax + q], so lanes touching neighbouring nodes hit
+// node q at tile[c * kTileCap<D> + q], so lanes touching neighbouring nodes hit
 // consecutive banks; the global grid is one float4 per node.
 template <int D, bool L>
 struct Nodes {
@@ -454,9 +460,9 @@ struct Nodes {
     const int q = idx(st, o0, o1, o2);
     if constexpr (L) {
       float4 v = make_float4(p[q], 0.f, 0.f, 0.f);
-      if (NC > 1) v.y = p[kTileMax + q];
-      if (NC > 2) v.z = p[2 * kTileMax + q];
-      if (NC > 3) v.w = p[3 * kTileMax + q];
+      if (NC > 1) v.y = p[kTileCap<D> + q];
+      if (NC > 2) v.z = p[2 * kTileCap<D> + q];
+      if (NC > 3) v.w = p[3 * kTileCap<D> + q];
       return v;
     } else {
       return reinterpret_cast<const float4*>(p)[q];
@@ -464,7 +470,7 @@ struct Nodes {
   }
   __device__ __forceinline__ void add(int q, int c, float v) const {
     if constexpr (L)
-      atomic_add_f32(p + c * kTileMax + q, v);
+      atomic_add_f32(p + c * kTileCap<D> + q, v);
     else
       atomic_add_f32(p + 4 * q + c, v);
   }
@@ -497,7 +503,7 @@ __device__ __forceinline__ Nodes<D, false> global_nodes(const float4* g, int n) 
 }
 
 // Scatter target: a box of the scene's grid in LDS, 64-bit fixed point with
-// scale 2^e, component c of tile node q at tile[c * kTileMax + q].
+// scale 2^e, component c of tile node q at tile[c * kTileCap<D> + q].
 template <int D>
 struct FixNodes {
   long long* p;
@@ -511,7 +517,7 @@ struct FixNodes {
     }
   }
   __device__ __forceinline__ void add(int q, int c, float v) const {
-    atomicAdd(reinterpret_cast<unsigned long long*>(p + c * kTileMax + q), (unsigned long long)to_fixed(v, e));
+    atomicAdd(reinterpret_cast<unsigned long long*>(p + c * kTileCap<D> + q), (unsigned long long)to_fixed(v, e));
   }
 };
 
@@ -674,7 +680,7 @@ __device__ __forceinline__ Tile<D> tile_of(const Box<D>& bx, bool one_scene) {
     ext[a] = bx.mx[a] - bx.mn[a] + 3;
   }
   tile_set_box<D>(T, lo, ext);
-  T.on = one_scene && T.n <= kTileMax;
+  T.on = one_scene && T.n <= kTileCap<D>;
   return T;
 }
 
@@ -717,7 +723,7 @@ __device__ __forceinline__ Tile<D> recorded_tile(const int4* table, int wg, int 
   }
   if (!inside) return T;
   tile_set_box<D>(T, lo, ext);
-  T.on = one_scene && l4.w == sc && T.n <= kTileMax;
+  T.on = one_scene && l4.w == sc && T.n <= kTileCap<D>;
   return T;
 }
 
@@ -816,7 +822,7 @@ __device__ __forceinline__ void tile_flush64(const Tile<D>& T, const long long* 
     bool nz = false;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      v[c] = tile[c * kTileMax + q];
+      v[c] = tile[c * kTileCap<D> + q];
       nz = nz || (v[c] != 0);
     }
     if (nz) {
@@ -1001,7 +1007,7 @@ __device__ __forceinline__ void node_adj(const StepConsts& k, const Sten<D>& st,
 }
 
 // Tile loads issue up to kTileBatch node loads per thread before using any,
-// so their latencies overlap (a box of up to kTileMax nodes takes one round
+// so their latencies overlap (a box of up to kTileCap<D> nodes takes one round
 // trip at 128 or more threads per workgroup).
 constexpr int kTileBatch = 4;
 
@@ -1026,7 +1032,7 @@ __device__ __forceinline__ void tile_load_vel(const StepConsts& k, const Tile<D>
         float v[D];
         grid_vel<D>(tile_node_interior<D>(c, k.n, k.bound) && gm[r].x > 0.0f, gm[r], k.gdt, v);
 #pragma unroll
-        for (int a = 0; a < D; ++a) tile[a * kTileMax + q] = v[a];
+        for (int a = 0; a < D; ++a) tile[a * kTileCap<D> + q] = v[a];
       }
     }
   }
@@ -1058,8 +1064,8 @@ __device__ __forceinline__ void tile_load_adj(const StepConsts& k, const Tile<D>
         float Pb[D], mb;
         grid_adj<D>(tile_node_interior<D>(c, k.n, k.bound) && gm[r].x > 0.0f, gm[r], vb4[r], Pb, mb);
 #pragma unroll
-        for (int a = 0; a < D; ++a) tile[a * kTileMax + q] = Pb[a];
-        tile[D * kTileMax + q] = mb;
+        for (int a = 0; a < D; ++a) tile[a * kTileCap<D> + q] = Pb[a];
+        tile[D * kTileCap<D> + q] = mb;
       }
     }
   }
@@ -1215,9 +1221,9 @@ __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i,
 
 // Zeroes the first NC components of a whole fixed-point tile (no barrier: the
 // next block reduction's barrier orders it before the scatter).
-template <int NC>
+template <int D, int NC>
 __device__ __forceinline__ void zero_tile64(long long* tile, int threads) {
-  for (int q = threadIdx.x; q < NC * kTileMax; q += threads) tile[q] = 0;
+  for (int q = threadIdx.x; q < NC * kTileCap<D>; q += threads) tile[q] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1270,8 +1276,8 @@ struct LaneMap {
 template <int D, int LPP>
 __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   constexpr int S0 = (LPP == 4) ? 1 : (LPP == 2 ? 2 : 3);
-  __shared__ long long tile64[(D + 1) * kTileMax];  // P2G scatter tile (fixed point)
-  __shared__ float vtile[D * kTileMax];              // G2P velocity tile
+  __shared__ long long tile64[(D + 1) * kTileCap<D>];  // P2G scatter tile (fixed point)
+  __shared__ float vtile[D * kTileCap<D>];              // G2P velocity tile
   __shared__ int red[64];
   const StepConsts& k = a.k;
   BlockRed rd{red, 0, (k.threads + 63) >> 6};
@@ -1290,7 +1296,7 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   if (live) load_state<D>(a.in, i, p);
   const ClearSpec c0{a.clear, a.clear_box, a.clear_nbox, a.clear_n}, c1{nullptr, nullptr, 0, 0};
   const ClearJobs cj = clear_jobs_fetch(c0, c1, k.groups);
-  if (a.do_p2g && k.lds) zero_tile64<D + 1>(tile64, k.threads);
+  if (a.do_p2g && k.lds) zero_tile64<D, D + 1>(tile64, k.threads);
   Tile<D> T = empty_tile<D>();
   const float4* g = a.grid_in + long(sc) * k.nodes;
   if (a.do_g2p && a.box_in) {
@@ -1343,9 +1349,9 @@ __device__ __forceinline__ void wave_add_keyed(bool live, int key, double val, d
 template <int D, int LPP>
 __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   constexpr int S0 = (LPP == 4) ? 1 : (LPP == 2 ? 2 : 3);
-  __shared__ float tA[(D + 1) * kTileMax];      // phase A: adjoint tile (P*, m*)
-  __shared__ float tV[D * kTileMax];            // phase B: velocity tile
-  __shared__ long long tS[(D + 1) * kTileMax];  // scatter tile: phase B (adjoint grid), phase C (grid)
+  __shared__ float tA[(D + 1) * kTileCap<D>];      // phase A: adjoint tile (P*, m*)
+  __shared__ float tV[D * kTileCap<D>];            // phase B: velocity tile
+  __shared__ long long tS[(D + 1) * kTileCap<D>];  // scatter tile: phase B (adjoint grid), phase C (grid)
   __shared__ int red[64];
   const StepConsts& k = a.k;
   BlockRed rd{red, 0, (k.threads + 63) >> 6};
@@ -1365,7 +1371,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   const ClearSpec c1{a.clear1, a.clear1_box, a.clear1_nbox, a.clear1_n};
   const ClearJobs cj = clear_jobs_fetch(c0, c1, k.groups);
   if (role_c) {
-    if (k.lds) zero_tile64<D + 1>(tS, k.threads);
+    if (k.lds) zero_tile64<D, D + 1>(tS, k.threads);
     PState<D> p;
     if (live) load_state<D>(a.stC, i, p);
     clear_jobs_run<D>(cj, c0, c1, k);
@@ -1415,7 +1421,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
         for (int b = 0; b < D; ++b) CnB[c][b] = a.cnext[(c * D + b) * a.cnext_stride + i];
     }
   }
-  if (!a.final_out && k.lds) zero_tile64<D>(tS, k.threads);
+  if (!a.final_out && k.lds) zero_tile64<D, D>(tS, k.threads);
   Tile<D> TA = empty_tile<D>(), TB = empty_tile<D>();
   if (a.a_mode == 1 && a.boxA_in) TA = recorded_tile<D>(a.boxA_in, wg, sc, one_scene, k.lds, k.n);
   if (!a.final_out && a.boxB_in) TB = recorded_tile<D>(a.boxB_in, wg, sc, one_scene, k.lds, k.n);
@@ -1626,7 +1632,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     PState<D> p;
     if (live) load_state<D>(a.stC, i, p);
     __syncthreads();  // every thread is done with the scatter tile of phase B
-    if (k.lds) zero_tile64<D + 1>(tS, k.threads);
+    if (k.lds) zero_tile64<D, D + 1>(tS, k.threads);
     p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
   }
   if (err) atomicOr(k.err, err);

@@ -56,7 +56,7 @@ def elastic3d_oracle_64():
 
 
 @pytest.mark.parametrize("knobs", [dict(block=64), dict(block=128), dict(block=256), dict(block=128, lanes=4),
-                                   dict(block=256, lanes=2), dict(block=64, lanes=2, rotate=0),
+                                   dict(block=256, lanes=2), dict(block=64, lanes=2, rotate=0), dict(block=192),
                                    dict(block=256, lanes=4, rotate=0), dict(block=128, lds=0, remap=1)])
 def test_elastic3d_parity_64_steps(knobs, elastic3d_oracle_64):
     """3D workload elastic3d (64^3 grid, 32768 particles) gated at 64 steps, in each
