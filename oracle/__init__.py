@@ -247,13 +247,16 @@ def actuation_bwd(W, b, omega, dt, T, abar):
 
 
 def loss_mean_pos(scene, state, axis, sign=1.0):
-    """L = sum over scenes of sign * (1/N_scene) sum_p x_{p,axis}; returns (L per scene, seed dL/dstate)."""
+    """L = sum over scenes of sign * (1/N_scene) sum_p x_{p,axis}; returns (L per scene, seed dL/dstate).
+    A scene with no particles contributes a zero term (and no seed entries)."""
     b = _Bound(scene)
     s = np.asarray(state, np.float64)
     L = np.zeros(b.n_scenes)
     seed = np.zeros_like(s)
     for k in range(b.n_scenes):
         lo, hi = b.offsets[k], b.offsets[k + 1]
+        if hi == lo:
+            continue
         L[k] = sign * s[lo:hi, axis].mean()
         seed[lo:hi, axis] = sign / (hi - lo)
     return L, seed

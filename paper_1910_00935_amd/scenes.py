@@ -73,11 +73,15 @@ class Scene:
     def with_steps(self, steps: int, ckpt_every: Optional[int] = None) -> "Scene":
         return replace(self, steps=int(steps), ckpt_every=self.ckpt_every if ckpt_every is None else ckpt_every)
 
-    def subset(self, scenes) -> "Scene":
-        """Scenes `scenes` of a batched scene, as a new batched scene."""
+    def subset(self, scenes, keep=None) -> "Scene":
+        """Scenes `scenes` of a batched scene (repeats allowed), as a new batched
+        scene. `keep[j]`, if given, keeps only the first keep[j] particles of the
+        j-th chosen scene (0 gives a scene with no particles)."""
         scenes = list(scenes)
-        idx = np.concatenate([np.arange(self.offsets[k], self.offsets[k + 1]) for k in scenes])
-        counts = [int(self.offsets[k + 1] - self.offsets[k]) for k in scenes]
+        full = [int(self.offsets[k + 1] - self.offsets[k]) for k in scenes]
+        counts = full if keep is None else [min(int(c), f) for c, f in zip(keep, full)]
+        idx = np.concatenate([np.arange(self.offsets[k], self.offsets[k] + c, dtype=np.int64)
+                              for k, c in zip(scenes, counts)])
         off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
         return replace(
             self, name=f"{self.name}[{len(scenes)}]", offsets=off, E=self.E[scenes].copy(),

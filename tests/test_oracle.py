@@ -306,6 +306,35 @@ def test_batch_independence():
         assert np.array_equal(g1, g0[lo:hi]) and gE1[0] == gE[j]
 
 
+def test_ragged_batch_with_empty_scenes():
+    """A batch holding scenes with no particles (first, in the middle, last), a
+    one-particle scene and truncated scenes: every non-empty scene gives bitwise
+    the outputs, loss term and gradients it gives alone; the empty scenes have a
+    zero loss term and a zero E gradient."""
+    base = scenes.batched2d(n_scenes=3, steps=8)
+    order, keep = [0, 0, 1, 2, 1, 2], [0, 1, 0, 37, 10 ** 9, 0]
+    full = base.subset(order, keep)
+    assert list(np.diff(full.offsets)) == [0, 1, 0, 37, base.offsets[2] - base.offsets[1], 0]
+    st = _state(full)
+    out, _, err = orc.run_fwd(full, 8, st)
+    assert err == 0
+    L, seed = orc.loss_mean_pos(full, out, 0)
+    g0, gE, _, _ = orc.run_bwd(full, 8, 8, st, seed)
+    for j, (k, c) in enumerate(zip(order, keep)):
+        lo, hi = full.offsets[j], full.offsets[j + 1]
+        if hi == lo:
+            assert L[j] == 0.0 and gE[j] == 0.0
+            continue
+        one = base.subset([k], [c])
+        s1 = _state(one)
+        o1, _, _ = orc.run_fwd(one, 8, s1)
+        assert np.array_equal(o1, out[lo:hi])
+        L1, sd1 = orc.loss_mean_pos(one, o1, 0)
+        assert L1[0] == L[j]
+        g1, gE1, _, _ = orc.run_bwd(one, 8, 8, s1, sd1)
+        assert np.array_equal(g1, g0[lo:hi]) and gE1[0] == gE[j]
+
+
 def _small_actuated(n_keep=300, steps=16):
     sc = scenes.actuated2d()
     keep = np.random.default_rng(0).choice(sc.n_particles, n_keep, replace=False)
