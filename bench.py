@@ -51,7 +51,8 @@ def _traffic(kernel_name, knobs):
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("source_hash") != _source_hash() or rec.get("knobs") != knobs:
+    from paper_1910_00935_amd.runtime import effective_knobs
+    if rec.get("source_hash") != _source_hash() or effective_knobs(rec.get("knobs")) != effective_knobs(knobs):
         return None
     k = rec.get("kernels", {}).get(kernel_name)
     return None if k is None else k.get("bytes_per_launch")
@@ -310,6 +311,29 @@ def run_batched(args, torch, rt, scenes, n_scenes=256, steps=256):
             "knobs_batched": knobs, "knobs_per_scene": knobs_one}
 
 
+def run_robot3d(args, torch, rt, scenes, iters=3):
+    """The 3D actuated robot (16 actuators, 30000 particles, 512 steps): open-loop
+    controller optimisation iterations (actuation signal, tape forward, loss,
+    reverse replay, actuation adjoint, weight update), timed after one warmup."""
+    from paper_1910_00935_amd.controller import OpenLoopController
+    sc = scenes.robot3d()
+    knobs = tuned_knobs(sc, args)
+    ctl = OpenLoopController(sc, knobs=knobs)
+    hist = [ctl.step(0.05)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        hist.append(ctl.step(0.05))
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    if ctl.sim.check_errors():
+        raise RuntimeError("robot3d: simulation error flags set")
+    return {"workload": f"3D actuated robot, 64^3 grid, {sc.n_particles} particles, {sc.n_act} actuators, "
+                        f"{sc.steps} steps; one optimisation iteration = fwd + loss + bwd + weight update",
+            "particle_steps_per_s": sc.n_particles * sc.steps * iters / secs,
+            "ms_per_iteration": secs * 1e3 / iters, "losses": [round(v, 6) for v in hist], "knobs": knobs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +344,7 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-robot", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default launch configuration")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune.json"))
     ap.add_argument("--knobs", default=None, help='launch configuration for the 3D workload as JSON, e.g. \'{"block": 256}\'')
@@ -387,6 +412,9 @@ def main():
     if not args.no_batched:
         print("[bench] batched 2D workload", flush=True)
         out["batched"] = run_batched(args, torch, rt, scenes)
+    if not args.no_robot:
+        print("[bench] 3D robot controller optimisation", flush=True)
+        out["robot3d"] = run_robot3d(args, torch, rt, scenes)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", flush=True)
         out["cpu_baseline"] = run_cpu_baseline(args.cpu_sample_steps)

@@ -157,7 +157,12 @@ mpm_status mpm_bind_workspace(mpm_ctx* ctx, void* dev, size_t bytes);
  * with 2, each lane of a pair visits half of the 3^d stencil (one in reverse
  * order) and the pair sums its gathers; with 4, three lanes each take one
  * slab and the quad sums its gathers; both raise parallelism for small
- * particle counts);
+ * particle counts); "part" (0/1, default 1: after each sort, cut the
+ * particles into workgroups along the Morton cell hierarchy, each packing
+ * consecutive child blocks of one block, so a workgroup's stencil footprint
+ * stays compact when particle density varies; the launch then has room for
+ * up to twice the plain number of workgroups, the unused ones empty; with 0,
+ * workgroups are runs of consecutive sorted particles);
  * "graph" (0/1, default 1:
  * capture each tape forward/backward launch sequence once in a HIP graph on
  * an internal stream and replay it on the caller's stream; the cache is keyed

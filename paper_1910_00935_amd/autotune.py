@@ -1,7 +1,7 @@
 """Launch-configuration autotuner for the step kernels.
 
 Times whole trajectories (tape forward + loss + tape backward) of a workload
-for each candidate knob set (`block`, `lanes`, `rotate`, `lds`, `split`) and
+for each candidate knob set (`block`, `lanes`, `part`, `rotate`, `lds`, `split`) and
 keeps the fastest. Results are cached in a JSON file keyed by the workload's
 shape (dimension, grid, particle and scene counts, steps) and the GPU
 architecture, so later runs of the same shape reuse them.
@@ -29,7 +29,8 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mpm_autotune.js
 SPACE = {
     "block": (128, 64, 192, 256),
     "lanes": (1, 2, 4),
-    "rotate": (1, 0),
+    "part": (1, 0),
+    "rotate": (1,),
     "lds": (1,),
     "split": (1,),
 }
@@ -39,7 +40,8 @@ def shape_key(scene, arch: Optional[str] = None) -> str:
     if arch is None:
         arch = torch.cuda.get_device_properties(0).gcnArchName if torch.cuda.is_available() else "cpu"
     desc = dict(dim=scene.dim, n_grid=scene.n_grid, N=scene.n_particles, scenes=scene.n_scenes,
-                steps=scene.steps, ckpt=scene.ckpt_every, act=scene.n_act, arch=arch)
+                steps=scene.steps, ckpt=scene.ckpt_every, act=scene.n_act, arch=arch,
+                knobs=sorted(SPACE))
     return hashlib.sha256(json.dumps(desc, sort_keys=True).encode()).hexdigest()[:20]
 
 

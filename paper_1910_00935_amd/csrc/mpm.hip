@@ -46,7 +46,9 @@ enum Region {
   R_GE,        // n_scenes double
   R_GACT,      // kMaxAct double (single-step adjoint)
   R_ERR,       // 1 uint32
-  R_BLOCKS,    // int4 per workgroup: scene-aligned particle ranges
+  R_BLOCKS,    // int4 per workgroup: scene-aligned particle ranges (first, count, scene)
+  R_PLAIN,     // int4 per workgroup: the plain partition (runs of consecutive particles)
+  R_PART,      // int32 per parent block: workgroups it emits, scanned
   R_BOXES,     // per grid, 2 int4 per workgroup: nodes its last scatter touched
   R_COUNT
 };
@@ -76,7 +78,10 @@ struct mpm_ctx {
   int rotate = 1;
   int lanes = 1;
   int graph = 1;
+  int part = 1;      // 1: workgroups aligned to the Morton cell hierarchy (rebuilt at each sort)
   int n_blocks = 0;  // workgroups per particle pass for the current block and lanes
+  int n_plain = 0;   // workgroups of the plain partition
+  long blocks_cap = 0;
   // What each grid holds, tracked while a launch sequence is enqueued: kZero,
   // kDirty (anything), or n >= 0: non-zero only inside the boxes its last
   // scatter (n workgroups) recorded in its R_BOXES table.
@@ -186,7 +191,7 @@ StepConsts consts(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
   k.lds = c.lds;
   k.remap = c.remap;
   k.rotate = c.rotate;
-  k.blocks = c.ns > 1 ? c.at<int4>(R_BLOCKS) : nullptr;
+  k.blocks = (c.ns > 1 || c.part) ? c.at<int4>(R_BLOCKS) : nullptr;
   k.n_blocks = c.n_blocks;
   k.E = p->E;
   k.nu = p->nu;
@@ -195,6 +200,22 @@ StepConsts consts(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
   k.act_id = (c.n_act > 0) ? act_id : nullptr;
   k.err = c.at<unsigned>(R_ERR);
   return k;
+}
+
+// Geometry of the cell hierarchy for the aligned partition (P particles per
+// workgroup).
+mpm::PartGeom part_geom(const mpm_ctx& c, int P) {
+  mpm::PartGeom g;
+  g.dim = c.d;
+  g.bits = c.bits;
+  g.P = P;
+  g.n_scenes = c.ns;
+  g.N = c.N;
+  g.n_keys = c.n_keys;
+  g.cells_per_scene = long(c.cells_per_scene);
+  g.per_scene = 0;
+  for (int l = 1; l <= c.bits; ++l) g.per_scene += 1 << (c.d * (c.bits - l));
+  return g;
 }
 
 const float* act_row(const mpm_ctx& c, const mpm_params* p, int s) {
@@ -313,7 +334,8 @@ mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& args, hipStream_t st) {
   span_step(c, 0, st);
   FwdArgs a = args;
   a.k.threads = c.block;
-  a.k.groups = c.n_blocks;
+  a.k.clear_per_role = c.part ? c.n_plain : c.n_blocks;
+  a.k.groups = a.k.clear_per_role;
   hipLaunchKernelGGL((mpm::k_fwd<D, LPP>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
   LAUNCH_TRY();
   return MPM_OK;
@@ -325,7 +347,8 @@ mpm_status launch_bwd(const mpm_ctx& c, const BwdArgs& args, hipStream_t st) {
   const int nb = c.n_blocks * (args.split_c ? 2 : 1);
   BwdArgs a = args;
   a.k.threads = c.block;
-  a.k.groups = nb;
+  a.k.clear_per_role = c.part ? c.n_plain : c.n_blocks;
+  a.k.groups = (args.split_c ? 2 : 1) * a.k.clear_per_role;
   hipLaunchKernelGGL((mpm::k_bwd<D, LPP>), dim3(nb), dim3(c.block), 0, st, a);
   LAUNCH_TRY();
   return MPM_OK;
@@ -364,7 +387,36 @@ BwdArgs bwd_args(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
   return a;
 }
 
-// Sorts particles by (scene, Morton cell) of `st`; writes R_PERM.
+// Aligned workgroup table from the cell starts of the last sort (R_START):
+// counts per parent block (into R_COUNTS, free after the sort), their scan,
+// the entries, and the padding (or the plain table if it did not fit).
+mpm_status build_partition(const mpm_ctx& c, hipStream_t s) {
+  const mpm::PartGeom g = part_geom(c, c.block / c.lanes);
+  const long n_par = long(g.per_scene) * g.n_scenes;
+  int* counts = c.at<int>(R_COUNTS);
+  int* offs = c.at<int>(R_PART);
+  const int pb = int((n_par + 255) / 256);
+  hipLaunchKernelGGL(mpm::k_part_count, dim3(pb), dim3(256), 0, s, c.at<int>(R_START), g, counts);
+  LAUNCH_TRY();
+  const int nb = int((n_par + mpm::kScanChunk - 1) / mpm::kScanChunk);
+  int* bsums = c.at<int>(R_BSUMS);
+  hipLaunchKernelGGL(mpm::k_scan_blocks, dim3(nb), dim3(mpm::kScanThreads), 0, s, counts, offs, n_par, bsums);
+  LAUNCH_TRY();
+  hipLaunchKernelGGL(mpm::k_scan_sums, dim3(1), dim3(mpm::kScanThreads), 0, s, bsums, nb);
+  LAUNCH_TRY();
+  hipLaunchKernelGGL(mpm::k_scan_add, dim3(nb), dim3(256), 0, s, offs, n_par, bsums);
+  LAUNCH_TRY();
+  hipLaunchKernelGGL(mpm::k_part_emit, dim3(pb), dim3(256), 0, s, c.at<int>(R_START), g, counts, offs, c.n_blocks,
+                     c.at<int4>(R_BLOCKS));
+  LAUNCH_TRY();
+  hipLaunchKernelGGL(mpm::k_part_finish, dim3(1), dim3(256), 0, s, g, counts, offs, c.n_blocks, c.at<int4>(R_PLAIN),
+                     c.n_plain, c.at<int4>(R_BLOCKS));
+  LAUNCH_TRY();
+  return MPM_OK;
+}
+
+// Sorts particles by (scene, Morton cell) of `st`; writes R_PERM (and, with
+// `part`, the aligned workgroup table).
 mpm_status sort_particles(const mpm_ctx& c, StateRef st, hipStream_t s) {
   span_close(c);
   int* counts = c.at<int>(R_COUNTS);
@@ -398,6 +450,7 @@ mpm_status sort_particles(const mpm_ctx& c, StateRef st, hipStream_t s) {
   hipLaunchKernelGGL(mpm::k_sort_fixup, dim3(int((nk + 255) / 256)), dim3(256), 0, s, c.at<int>(R_PERM), start, nk,
                      c.N);
   LAUNCH_TRY();
+  if (c.part) return build_partition(c, s);
   return MPM_OK;
 }
 
@@ -474,23 +527,32 @@ mpm_status ensure_state(mpm_tape& tp, const mpm_params* p, int step, hipStream_t
   return run_forward(tp, p, t0, t1, s);
 }
 
-// Workgroup table for the current block size and lanes: one scene per
-// workgroup when there are several scenes (uploaded to R_BLOCKS), else plain
-// ceil(N / particles per workgroup).
+// Workgroup table for the current block and lanes. The plain partition cuts
+// each scene into runs of consecutive particles. With `part`, the launch has
+// room for the aligned partition (at most twice as many workgroups, rebuilt
+// on the device after each sort; trailing entries are empty workgroups), and
+// the table starts as the plain one padded with empty entries, so launches
+// before the first sort (single steps) are valid too.
 mpm_status update_blocks(mpm_ctx& c) {
   const int per_block = c.block / c.lanes;
-  if (c.ns <= 1) {
-    c.n_blocks = (c.N + per_block - 1) / per_block;
-    return MPM_OK;
-  }
   std::vector<int4> t;
   for (int sc = 0; sc < c.ns; ++sc)
     for (int f = c.offsets[sc]; f < c.offsets[sc + 1]; f += per_block)
       t.push_back(make_int4(f, std::min(per_block, c.offsets[sc + 1] - f), sc, 0));
   if (t.empty()) t.push_back(make_int4(0, 0, 0, 0));
-  if (t.size() * sizeof(int4) > c.bytes[R_BLOCKS]) return MPM_E_CAPACITY;
-  c.n_blocks = int(t.size());
-  if (c.ws) HIP_TRY(hipMemcpy(c.at<int4>(R_BLOCKS), t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
+  if (t.size() * sizeof(int4) > c.bytes[R_PLAIN]) return MPM_E_CAPACITY;
+  c.n_plain = int(t.size());
+  if (!c.part && c.ns <= 1) {
+    c.n_blocks = (c.N + per_block - 1) / per_block;
+    return MPM_OK;
+  }
+  c.n_blocks = c.part ? 2 * c.n_plain + 32 : c.n_plain;
+  if (c.n_blocks > c.blocks_cap || c.n_blocks > c.box_cap) return MPM_E_CAPACITY;
+  if (c.ws) {
+    HIP_TRY(hipMemcpy(c.at<int4>(R_PLAIN), t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
+    t.resize(size_t(c.n_blocks), make_int4(0, 0, 0, 0));
+    HIP_TRY(hipMemcpy(c.at<int4>(R_BLOCKS), t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
+  }
   return MPM_OK;
 }
 
@@ -577,9 +639,14 @@ mpm_status mpm_init(const mpm_desc* desc, mpm_ctx** out) {
   c->bytes[R_GE] = size_t(c->ns) * sizeof(double);
   c->bytes[R_GACT] = size_t(mpm::kMaxAct) * sizeof(double);
   c->bytes[R_ERR] = sizeof(unsigned);
-  // At least 16 particles per workgroup (64 threads, 4 lanes each).
-  c->bytes[R_BLOCKS] = (c->ns > 1) ? (N / 16 + size_t(c->ns) + 1) * sizeof(int4) : 0;
-  c->box_cap = long(N / 16 + size_t(c->ns) + 1);
+  // At least 16 particles per workgroup (64 threads, 4 lanes each); the
+  // aligned partition may use up to twice the plain one's workgroups.
+  const size_t plain_max = N / 16 + size_t(c->ns) + 1;
+  c->blocks_cap = long(2 * plain_max + 32);
+  c->bytes[R_BLOCKS] = size_t(c->blocks_cap) * sizeof(int4);
+  c->bytes[R_PLAIN] = plain_max * sizeof(int4);
+  c->bytes[R_PART] = size_t(part_geom(*c, 16).per_scene) * size_t(c->ns) * sizeof(int);
+  c->box_cap = c->blocks_cap;
   c->bytes[R_BOXES] = size_t(kNumGrids) * 2 * size_t(c->box_cap) * sizeof(int4);
   size_t o = 0;
   for (int r = 0; r < R_COUNT; ++r) {
@@ -649,6 +716,11 @@ mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value) {
     if (value != 0 && value != 1) return MPM_E_ARG;
     ctx->remap = int(value);
     return MPM_OK;
+  }
+  if (k == "part") {
+    if (value != 0 && value != 1) return MPM_E_ARG;
+    ctx->part = int(value);
+    return update_blocks(*ctx);
   }
   if (k == "split") {
     if (value != 0 && value != 1) return MPM_E_ARG;
@@ -942,6 +1014,7 @@ std::vector<uintptr_t> graph_key(const mpm_tape* tape, int kind, const mpm_param
   const mpm_ctx& c = *tape->ctx;
   std::vector<uintptr_t> k = {uintptr_t(kind), reinterpret_cast<uintptr_t>(c.ws), reinterpret_cast<uintptr_t>(tape->mem),
                               uintptr_t(c.block), uintptr_t(c.lds), uintptr_t(c.split_c), uintptr_t(c.remap), uintptr_t(c.rotate), uintptr_t(c.lanes),
+                              uintptr_t(c.part),
                               reinterpret_cast<uintptr_t>(p->E), reinterpret_cast<uintptr_t>(p->nu),
                               reinterpret_cast<uintptr_t>(p->vol), reinterpret_cast<uintptr_t>(p->rho),
                               reinterpret_cast<uintptr_t>(p->act_id), reinterpret_cast<uintptr_t>(p->act),

@@ -64,7 +64,8 @@ struct StepConsts {
                         // several scenes, null with one
   int n_blocks;         // workgroups per particle pass
   int threads;          // threads per workgroup of this launch (blockDim.x, kept in a scalar register)
-  int groups;           // workgroups of this launch (gridDim.x)
+  int groups;           // workgroups that share the launch's clears (their clear ranks 0..groups-1)
+  int clear_per_role;   // of each role's n_blocks workgroups, the first clear_per_role take part in clears
   const float* E;
   const float* nu;
   const float* vol;
@@ -216,10 +217,10 @@ __device__ __forceinline__ bool node_active(const Sten<D>& st, int o0, int o1, i
   return in && m > 0.0f;
 }
 
-__device__ __forceinline__ void zero_range(float4* p, long n, int threads, int groups) {
-  if (!p) return;
+__device__ __forceinline__ void zero_range(float4* p, long n, int threads, int groups, int rank) {
+  if (!p || rank < 0) return;
   const long stride = long(groups) * threads;
-  for (long q = long(blockIdx.x) * threads + threadIdx.x; q < n; q += stride) p[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (long q = long(rank) * threads + threadIdx.x; q < n; q += stride) p[q] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // Read of a value that is uniform over the workgroup and was written by an
@@ -308,13 +309,23 @@ __device__ __forceinline__ void clear_entry(const ClearSpec& s0, const ClearSpec
   ex = load_uniform(t + 2 * jj + 1);
 }
 
-__device__ __forceinline__ ClearJobs clear_jobs_fetch(const ClearSpec& s0, const ClearSpec& s1, int groups) {
+// Clear rank of a workgroup: its index among the workgroups that take part in
+// the launch's clears, or -1. Of each role's n_blocks workgroups (one role, or
+// two with a separate recompute role), the first clear_per_role do; the
+// aligned partition's trailing empty workgroups therefore never do.
+__device__ __forceinline__ int clear_rank(const StepConsts& k, int wg, bool second_role) {
+  if (wg >= k.clear_per_role) return -1;
+  return second_role ? k.clear_per_role + wg : wg;
+}
+
+__device__ __forceinline__ ClearJobs clear_jobs_fetch(const ClearSpec& s0, const ClearSpec& s1, int rank, int groups) {
   ClearJobs c;
   c.n = 0;
+  if (rank < 0) return c;
   const int m = clear_entries(s0) + clear_entries(s1);
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
-    const int j = int(blockIdx.x) + r * groups;
+    const int j = rank + r * groups;
     if (j < m) {
       clear_entry(s0, s1, j, c.lo[r], c.ex[r], c.which[r]);
       c.n = r + 1;
@@ -325,20 +336,21 @@ __device__ __forceinline__ ClearJobs clear_jobs_fetch(const ClearSpec& s0, const
 
 template <int D>
 __device__ __forceinline__ void clear_jobs_run(const ClearJobs& c, const ClearSpec& s0, const ClearSpec& s1,
-                                               const StepConsts& k) {
+                                               const StepConsts& k, int rank) {
+  if (rank < 0) return;
 #pragma unroll
   for (int r = 0; r < 2; ++r)
     if (r < c.n)
       clear_box_nodes<D>(c.which[r] == 0 ? s0.g : s1.g, c.lo[r], c.ex[r], k.n, k.nodes, k.n_scenes, k.threads);
   const int m = clear_entries(s0) + clear_entries(s1);
-  for (int j = int(blockIdx.x) + 2 * k.groups; j < m; j += k.groups) {
+  for (int j = rank + 2 * k.groups; j < m; j += k.groups) {
     int4 lo, ex;
     int which;
     clear_entry(s0, s1, j, lo, ex, which);
     clear_box_nodes<D>(which == 0 ? s0.g : s1.g, lo, ex, k.n, k.nodes, k.n_scenes, k.threads);
   }
-  if (s0.g && !s0.box) zero_range(s0.g, s0.dense_n, k.threads, k.groups);
-  if (s1.g && !s1.box) zero_range(s1.g, s1.dense_n, k.threads, k.groups);
+  if (s0.g && !s0.box) zero_range(s0.g, s0.dense_n, k.threads, k.groups, rank);
+  if (s1.g && !s1.box) zero_range(s1.g, s1.dense_n, k.threads, k.groups, rank);
 }
 
 __device__ __forceinline__ void atomic_add_f32(float* p, float v) { unsafeAtomicAdd(p, v); }
@@ -1288,6 +1300,11 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   const int sc = lm.scene;
   const bool one_scene = true;
   unsigned err = 0;
+  const int rank = clear_rank(k, int(blockIdx.x), false);
+  if (k.blocks && lm.count == 0 && rank < 0) {  // an unused entry of the aligned partition
+    if (a.do_p2g) record_box<D>(a.box_out, int(blockIdx.x), empty_tile<D>(), -1);
+    return;
+  }
   // Every independent global read is issued first: the state, the clear
   // boxes, and the G2P box recorded by the scatter into grid_in (the previous
   // launch), so the tile load needs neither this launch's positions nor a
@@ -1295,7 +1312,7 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   PState<D> p;
   if (live) load_state<D>(a.in, i, p);
   const ClearSpec c0{a.clear, a.clear_box, a.clear_nbox, a.clear_n}, c1{nullptr, nullptr, 0, 0};
-  const ClearJobs cj = clear_jobs_fetch(c0, c1, k.groups);
+  const ClearJobs cj = clear_jobs_fetch(c0, c1, rank, k.groups);
   if (a.do_p2g && k.lds) zero_tile64<D, D + 1>(tile64, k.threads);
   Tile<D> T = empty_tile<D>();
   const float4* g = a.grid_in + long(sc) * k.nodes;
@@ -1312,7 +1329,7 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
       if (T.on) tile_load_vel<D>(k, T, g, vtile);
     }
     if (T.on) __syncthreads();
-    clear_jobs_run<D>(cj, c0, c1, k);
+    clear_jobs_run<D>(cj, c0, c1, k, rank);
     if (ok) {
       if (T.on && in_tile<D>(T, st.base))
         g2p_body<D, true, S0>(k, st, lds_nodes<D>(vtile, T), p);
@@ -1323,7 +1340,7 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
     }
     if (live && lm.owner) store_state<D>(a.out, i, p);
   } else {
-    clear_jobs_run<D>(cj, c0, c1, k);
+    clear_jobs_run<D>(cj, c0, c1, k, rank);
   }
   if (a.do_p2g)
     p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_row, a.grid_out, tile64, rd, err, a.box_out,
@@ -1367,14 +1384,24 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   const int sc = lm.scene;
   const bool one_scene = true;
   unsigned err = 0;
+  const int rank = clear_rank(k, wg, role_c);
+  if (k.blocks && lm.count == 0 && rank < 0) {  // an unused entry of the aligned partition
+    if (role_c) {
+      record_box<D>(a.boxC, wg, empty_tile<D>(), -1);
+    } else {
+      if (!a.final_out) record_box<D>(a.boxB, wg, empty_tile<D>(), -1);
+      if (a.do_c && !a.split_c) record_box<D>(a.boxC, wg, empty_tile<D>(), -1);
+    }
+    return;
+  }
   const ClearSpec c0{a.clear0, a.clear0_box, a.clear0_nbox, a.clear0_n};
   const ClearSpec c1{a.clear1, a.clear1_box, a.clear1_nbox, a.clear1_n};
-  const ClearJobs cj = clear_jobs_fetch(c0, c1, k.groups);
+  const ClearJobs cj = clear_jobs_fetch(c0, c1, rank, k.groups);
   if (role_c) {
     if (k.lds) zero_tile64<D, D + 1>(tS, k.threads);
     PState<D> p;
     if (live) load_state<D>(a.stC, i, p);
-    clear_jobs_run<D>(cj, c0, c1, k);
+    clear_jobs_run<D>(cj, c0, c1, k, rank);
     p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
     if (err) atomicOr(k.err, err);
     return;
@@ -1501,7 +1528,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   }
 
   if (a.final_out) {
-    clear_jobs_run<D>(cj, c0, c1, k);
+    clear_jobs_run<D>(cj, c0, c1, k, rank);
     if (!live || !owner) return;
     const int o = a.out_perm ? a.out_perm[i] : i;
     const int os = a.out.stride;
@@ -1543,7 +1570,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
       if (T.on) tile_load_vel<D>(k, T, g, tV);
     }
     if (T.on) __syncthreads();
-    clear_jobs_run<D>(cj, c0, c1, k);
+    clear_jobs_run<D>(cj, c0, c1, k, rank);
     const bool in_t = T.on && ok && in_tile<D>(T, st.base);
     float Bm[D][D] = {}, vt[D] = {}, bound = 0.0f;
     if (ok) {

@@ -142,6 +142,106 @@ __global__ void k_sort_fixup(int* perm, const int* start, long n_keys, int N) {
   }
 }
 
+// Workgroup partition aligned to the Morton cell hierarchy, built from the
+// cell starts of the last sort. A block of level l is 2^(D l) consecutive keys
+// of one scene (a cube of 2^l cells per axis). A block holding more than P
+// particles (P = particles per workgroup) is split: its 2^D children, in key
+// order, are packed greedily into workgroups of at most P particles (runs of
+// consecutive children only), a child holding more than P particles being
+// split in turn; a single cell holding more than P particles is cut into runs
+// of P. A scene holding at most P particles is one workgroup. Every workgroup
+// therefore lies inside one block whose children it packs, so its particles
+// span at most 2^l + 2 nodes per axis (the stencil adds two), unlike runs of P
+// consecutive particles, which straddle distant blocks where the Morton curve
+// jumps. One thread per block of level >= 1 (a parent), in the order
+// (scene, level, block); k_part_visit counts (out null) or writes the
+// workgroups that parent emits.
+struct PartGeom {
+  int dim, bits, P, n_scenes, N;
+  long n_keys;
+  long cells_per_scene;
+  int per_scene;  // parents per scene: sum over l = 1..bits of 2^(dim (bits - l))
+};
+
+__device__ __forceinline__ int part_start(const int* start, const PartGeom& g, long key) {
+  return key < g.n_keys ? start[key] : g.N;
+}
+
+__device__ __forceinline__ int part_visit(const int* start, const PartGeom& g, int t, int4* out) {
+  const int sc = t / g.per_scene;
+  int r = t - sc * g.per_scene;
+  int l = 1;
+  for (; l < g.bits; ++l) {
+    const int nb = 1 << (g.dim * (g.bits - l));
+    if (r < nb) break;
+    r -= nb;
+  }
+  const long size = 1L << (g.dim * l), csize = size >> g.dim;
+  const long b0 = long(sc) * g.cells_per_scene + long(r) * size;
+  const int f0 = part_start(start, g, b0);
+  const int cnt = part_start(start, g, b0 + size) - f0;
+  int emitted = 0;
+  auto emit = [&](int first, int count) {
+    if (out) out[emitted] = make_int4(first, count, sc, 0);
+    ++emitted;
+  };
+  if (cnt <= g.P) {
+    if (l == g.bits && cnt > 0) emit(f0, cnt);  // the whole scene
+    return emitted;
+  }
+  int cur_f = 0, cur_n = 0;
+  for (int ch = 0; ch < (1 << g.dim); ++ch) {
+    const long c0 = b0 + ch * csize;
+    const int cf = part_start(start, g, c0);
+    const int cc = part_start(start, g, c0 + csize) - cf;
+    if (cc > g.P) {
+      if (cur_n) emit(cur_f, cur_n);
+      cur_n = 0;
+      if (l == 1)
+        for (int f = cf; f < cf + cc; f += g.P) emit(f, min(g.P, cf + cc - f));
+    } else if (cc > 0) {
+      if (cur_n + cc > g.P) {
+        emit(cur_f, cur_n);
+        cur_n = 0;
+      }
+      if (cur_n == 0) cur_f = cf;
+      cur_n += cc;
+    }
+  }
+  if (cur_n) emit(cur_f, cur_n);
+  return emitted;
+}
+
+__global__ void k_part_count(const int* start, PartGeom g, int* counts) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.per_scene * g.n_scenes) return;
+  counts[t] = part_visit(start, g, t, nullptr);
+}
+
+// offs: exclusive scan of the counts. Writes only if the partition fits in cap.
+__global__ void k_part_emit(const int* start, PartGeom g, const int* counts, const int* offs, int cap, int4* table) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n_par = g.per_scene * g.n_scenes;
+  if (t >= n_par) return;
+  const int total = offs[n_par - 1] + counts[n_par - 1];
+  if (total > cap || counts[t] == 0) return;
+  part_visit(start, g, t, table + offs[t]);
+}
+
+// Pads the table to cap entries with empty workgroups (count 0); if the
+// partition did not fit, writes the plain one (n_plain entries) instead.
+__global__ void k_part_finish(PartGeom g, const int* counts, const int* offs, int cap, const int4* plain,
+                              int n_plain, int4* table) {
+  const int n_par = g.per_scene * g.n_scenes;
+  const int total = offs[n_par - 1] + counts[n_par - 1];
+  int used = total;
+  if (total > cap) {
+    for (int j = threadIdx.x; j < n_plain; j += blockDim.x) table[j] = plain[j];
+    used = n_plain;
+  }
+  for (int j = used + int(threadIdx.x); j < cap; j += blockDim.x) table[j] = make_int4(0, 0, 0, 0);
+}
+
 // dst[i] = src[perm[i]] for all S components (perm null: identity).
 template <int D>
 __global__ void k_gather_state(StateRef src, StateRef dst, const int* perm, int N) {

@@ -91,6 +91,16 @@ class Params:
                             _ptr(self.act))
 
 
+# The library's knob defaults (mpm_set_knob in mpm.h), for comparing launch
+# configurations given as partial dicts.
+DEFAULT_KNOBS = {"block": 128, "lanes": 1, "part": 1, "rotate": 1, "lds": 1, "split": 1, "remap": 0}
+
+
+def effective_knobs(knobs: Optional[dict]) -> dict:
+    """The full launch configuration a partial knob dict selects."""
+    return {**DEFAULT_KNOBS, **(knobs or {})}
+
+
 class Simulator:
     """One context: a description (grid, time step, scenes) plus bound workspace."""
 

@@ -19,6 +19,8 @@ benchmark used a 2D scene with 6.4K particles whose grid is not stated):
   elastic3d_long   3D, 128^3 grid, 262144 particles on a 64^3 lattice, 1024 steps, checkpoints every 64
   batched2d   256 independent 2D scenes on their own 64^2 grids, particle counts
        log-uniform in [500, 8000], per-scene E and nu, 256 steps
+  robot3d   3D actuated soft robot (body on four legs), 64^3 grid, 30000 particles,
+       16 actuators, 512 steps (the crawler of Appendix E.1, synthetic geometry)
   fd8  8 particles with random C and F, for finite-difference checks
 """
 from __future__ import annotations
@@ -225,6 +227,46 @@ def elastic3d_long(seed: int = 3) -> Scene:
     return _lattice3d("elastic3d_long", seed, 128, 64, 2.5e-4, 1024, 64, 0)
 
 
+def robot3d(seed: int = 5, n_particles: int = 30000, steps: int = 512) -> Scene:
+    """3D actuated soft robot (the crawler of Appendix E.1: 16 muscles, about 30K
+    particles; the paper gives no geometry, so this one is synthetic): 64^3 grid;
+    a body slab [0.1, 0.45] x [0.15, 0.225] x [0.3, 0.65] standing on four legs
+    0.1 x 0.1 x 0.1 at its corners (feet at y = 0.05, just above the sticky floor
+    band); particles uniform in the five boxes, in proportion to volume. Each leg
+    is split into 2 x 2 columns in x-z, one actuator per column (16 actuators);
+    the body is passive. a_k(t) as in actuated2d with n_sin = 4, W, b ~ N(0, 0.1^2),
+    omega = 2 pi 8, sigma_a = 10; E = 20, nu = 0.3, dt = 5e-4, 512 steps, v0 = 0;
+    loss = -(mean final x), i.e. crawl towards +x."""
+    rng = np.random.default_rng(seed)
+    n = 64
+    body = ((0.10, 0.45), (0.15, 0.225), (0.30, 0.65))
+    legs = [((x0, x0 + 0.1), (0.05, 0.15), (z0, z0 + 0.1)) for x0 in (0.10, 0.35) for z0 in (0.30, 0.55)]
+    boxes = [body] + legs
+    vols = np.array([np.prod([hi - lo for lo, hi in b]) for b in boxes])
+    counts = np.floor(n_particles * vols / vols.sum()).astype(int)
+    counts[0] += n_particles - counts.sum()
+    xs, act = [], []
+    for k, (b, c) in enumerate(zip(boxes, counts)):
+        lo = np.array([r[0] for r in b])
+        hi = np.array([r[1] for r in b])
+        pts = rng.uniform(lo, hi, size=(c, 3))
+        xs.append(pts)
+        if k == 0:
+            act.append(np.full(c, -1))
+        else:
+            mid = 0.5 * (lo + hi)
+            act.append(4 * (k - 1) + 2 * (pts[:, 0] >= mid[0]) + (pts[:, 2] >= mid[2]))
+    x = np.concatenate(xs)
+    n_act = 16
+    W = rng.normal(0.0, 0.1, size=(n_act, 4))
+    bb = rng.normal(0.0, 0.1, size=(n_act,))
+    s = _single("robot3d", 3, n, 5e-4, steps, x, np.zeros_like(x), 20.0, 0.3, float(vols.sum()) / n_particles,
+                loss_axis=0, loss_sign=-1.0, act_id=np.concatenate(act).astype(np.int32), n_act=n_act,
+                act_strength=10.0, act_W=_f32(W), act_b=_f32(bb), act_omega=float(F32(2 * math.pi * 8)))
+    s.meta["boxes"] = boxes
+    return s
+
+
 def batched2d(seed: int = 4, n_scenes: int = 256, steps: int = 256) -> Scene:
     """n_scenes independent 2D scenes, each on its own 64^2 grid, with particle counts
     N = round(exp U(ln 500, ln 8000)) in rectangle-union shapes (4 particles per cell,
@@ -295,7 +337,8 @@ def random_state(scene: Scene, seed: int, c_scale: float = 1.0, f_scale: float =
                    F=_f32(np.eye(d) + f_scale * rng.normal(0, 1, (N, d, d))))
 
 
-REGISTRY = {"translate2d": translate2d, "deform2d": deform2d, "actuated2d": actuated2d, "elastic3d": elastic3d, "elastic3d_long": elastic3d_long, "batched2d": batched2d}
+REGISTRY = {"translate2d": translate2d, "deform2d": deform2d, "actuated2d": actuated2d, "elastic3d": elastic3d, "elastic3d_long": elastic3d_long, "batched2d": batched2d,
+            "robot3d": robot3d}
 
 
 def make(name: str, **kw) -> Scene:

@@ -113,6 +113,9 @@ def test_knobs_and_status_strings():
         L.mpm_set_knob(ctx, "block", 128)
         assert L.lib().mpm_set_knob(ctx, b"block", 100) == L.MPM_E_ARG
         assert L.lib().mpm_set_knob(ctx, b"nope", 1) == L.MPM_E_ARG
+        for v in (0, 1):
+            assert L.lib().mpm_set_knob(ctx, b"part", v) == L.MPM_OK
+        assert L.lib().mpm_set_knob(ctx, b"part", 2) == L.MPM_E_ARG
     finally:
         L.mpm_destroy(ctx)
     for code in range(9):

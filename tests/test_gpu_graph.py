@@ -109,3 +109,24 @@ def test_launch_shape_change_between_trajectories():
     assert min(cos(second[1][k], fresh[1][k]) for k in range(4)) > 0.99999
     assert rel(first[0], fresh[0]) < 1e-4
     assert sim.check_errors() == 0
+
+
+def test_partition_change_between_trajectories():
+    """One context, the workgroup partition switched between trajectories (plain,
+    aligned, plain): same trajectories and gradients as fresh contexts."""
+    sc = scenes.robot3d().with_steps(16)
+    w = random_seed(sc, 6)
+    p = rt.params_for_scene(sc)
+    init = rt.state_for_scene(sc)
+    sim = rt.Simulator.for_scene(sc, knobs={"block": 256, "part": 0})
+    outs = []
+    for part in (0, 1, 0):
+        sim.set_knob("part", part)
+        outs.append(_run(sim, sc, sim.tape(16, 4), p, init, w)[0])
+    for part, got in zip((0, 1, 0), outs):
+        fresh_sim = rt.Simulator.for_scene(sc, knobs={"block": 256, "part": part})
+        ref = _run(fresh_sim, sc, fresh_sim.tape(16, 4), p, init, w)[0]
+        assert rel(got[0], ref[0]) < 1e-6
+        assert min(cos(got[1][k], ref[1][k]) for k in range(4)) > 0.99999
+    assert sim.check_errors() == 0
+

@@ -57,7 +57,8 @@ def elastic3d_oracle_64():
 
 @pytest.mark.parametrize("knobs", [dict(block=64), dict(block=128), dict(block=256), dict(block=128, lanes=4),
                                    dict(block=256, lanes=2), dict(block=64, lanes=2, rotate=0), dict(block=192),
-                                   dict(block=256, lanes=4, rotate=0), dict(block=128, lds=0, remap=1)])
+                                   dict(block=256, lanes=4, rotate=0), dict(block=128, lds=0, remap=1),
+                                   dict(block=256, part=0), dict(block=64, lanes=4, part=0)])
 def test_elastic3d_parity_64_steps(knobs, elastic3d_oracle_64):
     """3D workload elastic3d (64^3 grid, 32768 particles) gated at 64 steps, in each
     launch configuration."""
@@ -92,24 +93,37 @@ def test_batched2d_batched_subset(lanes):
     compare("batched2d[6]@160 random functional", full, g, o, grads=("x", "v", "C", "F"))
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4])
-def test_ragged_batch_with_empty_scenes(lanes):
+@pytest.mark.parametrize("lanes,part", [(1, 1), (2, 1), (4, 1), (1, 0)])
+def test_ragged_batch_with_empty_scenes(lanes, part):
     """Scenes with no particles (first, in the middle, last), a one-particle
     scene and scenes whose counts leave ragged workgroups, in one batch: loss
     terms, trajectories and gradients match the oracle; the empty scenes have
     zero loss terms and zero E gradients."""
     base = scenes.batched2d(n_scenes=4, steps=160)
     full = base.subset([0, 0, 1, 2, 3, 1, 2], [0, 1, 0, 37, 257, 10 ** 9, 0])
-    log(f"[ragged] counts {list(np.diff(full.offsets))}, lanes {lanes}")
-    g = gpu_run(full, 64, knobs={"lanes": lanes})
+    log(f"[ragged] counts {list(np.diff(full.offsets))}, lanes {lanes}, part {part}")
+    g = gpu_run(full, 64, knobs={"lanes": lanes, "part": part})
     o = oracle_run(full, 64)
     compare("ragged@64", full, g, o, grads=("v",), check_E=False)
     empty = np.diff(full.offsets) == 0
     assert np.all(g["loss"][empty] == 0) and np.all(o["loss"][empty] == 0)
     assert rel(g["loss"], o["loss"]) < 1e-5, (g["loss"], o["loss"])
     w = random_seed(full, 6)
-    g = gpu_run(full, 160, seed=w, knobs={"lanes": lanes})
+    g = gpu_run(full, 160, seed=w, knobs={"lanes": lanes, "part": part})
     o = oracle_run(full, 160, seed=w)
     compare("ragged@160 random functional", full, g, o, grads=("x", "v", "C", "F"))
     assert np.all(g["gE"][empty] == 0) and np.all(o["gE"][empty] == 0)
+
+
+@pytest.mark.parametrize("part", [0, 1])
+def test_robot3d_partitions(part):
+    """The 3D robot (uniform random particles, so runs of consecutive sorted
+    particles straddle distant Morton blocks) over 48 steps with the plain and
+    the aligned workgroup partition, both against the oracle."""
+    sc = scenes.robot3d().with_steps(48)
+    act = act_table(sc, 48)
+    w = random_seed(sc, 8)
+    g = gpu_run(sc, 48, act=act, seed=w, knobs={"block": 256, "part": part})
+    o = oracle_run(sc, 48, act=act, seed=w)
+    compare(f"robot3d@48 part={part}", sc, g, o, grads=("x", "v", "C", "F"))
 

@@ -335,12 +335,33 @@ def test_ragged_batch_with_empty_scenes():
         assert np.array_equal(g1, g0[lo:hi]) and gE1[0] == gE[j]
 
 
-def _small_actuated(n_keep=300, steps=16):
-    sc = scenes.actuated2d()
-    keep = np.random.default_rng(0).choice(sc.n_particles, n_keep, replace=False)
-    keep.sort()
+def _small_actuated(n_keep=300, steps=16, name="actuated2d"):
+    """A random subset of an actuated scene; for the 3D robot, of one leg (actuators
+    0-3), so that the kept particles are close enough to interact."""
+    sc = scenes.make(name)
+    pool = np.arange(sc.n_particles) if name == "actuated2d" else np.flatnonzero((sc.act_id >= 0) & (sc.act_id < 4))
+    keep = np.sort(np.random.default_rng(0).choice(pool, n_keep, replace=False))
     return replace(sc, steps=steps, offsets=np.array([0, n_keep], np.int32), x=sc.x[keep], v=sc.v[keep],
                    C=sc.C[keep], F=sc.F[keep], act_id=sc.act_id[keep])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_actuation_stress_closed_form(dim):
+    """One particle at rest with F = I (no elastic stress) on actuator 0 with signal
+    a: the stress read back through the grid's second moment (as in the neo-Hookean
+    closed-form pin) is sigma_a a on the (y, y) entry and zero elsewhere."""
+    n = 16
+    dx = 1.0 / n
+    x = np.array([7.3, 8.6, 7.9][:dim]) * dx
+    sc = replace(_one_particle(dim, x, n=n), act_id=np.array([0], np.int32), n_act=1, act_strength=10.0)
+    a = 0.37
+    gp, _, err = orc.grid(sc, _state(sc), act_s=np.array([a]))
+    assert err == 0
+    delta = _node_coords(n, dim) * dx - x
+    tau = -(gp[0, :, 1:].T @ delta) / (sc.dt * sc.vol[0])
+    expect = np.zeros((dim, dim))
+    expect[1, 1] = 10.0 * a
+    np.testing.assert_allclose(tau, expect, rtol=1e-12, atol=1e-12)
 
 
 def test_actuation_signal_closed_form():
@@ -351,10 +372,13 @@ def test_actuation_signal_closed_form():
     np.testing.assert_allclose(a[0], np.tanh(W[:, 1] - W[:, 3] + b), rtol=1e-15, atol=1e-15)
 
 
-def test_actuation_chain_fd():
+@pytest.mark.parametrize("name,steps,h", [("actuated2d", 16, 1e-6), ("robot3d", 48, 1e-4)])
+def test_actuation_chain_fd(name, steps, h):
     """dL/dW and dL/db through the actuation stress (sigma_a a_k e_y e_y^T) and the
-    tanh-of-sinusoids signal, against central differences of the oracle forward."""
-    sc = _small_actuated()
+    tanh-of-sinusoids signal, against central differences of the oracle forward.
+    (The 3D leg moves little, so it runs longer with a larger step h, keeping the
+    difference above rounding noise; the truncation error stays O(h^2).)"""
+    sc = _small_actuated(name=name, steps=steps)
     T = sc.steps
     st = _state(sc)
     W0 = sc.act_W.astype(np.float64)
@@ -370,7 +394,6 @@ def test_actuation_chain_fd():
     _, seed = orc.loss_mean_pos(sc, out, 0, -1.0)
     _, _, gact, _ = orc.run_bwd(sc, T, T, st, seed, act=a)
     gW, gb = orc.actuation_bwd(W0, b0, sc.act_omega, sc.dt, T, gact)
-    h = 1e-6
     for (k, j) in [(0, 1), (2, 3), (3, 0)]:
         Wp, Wm = W0.copy(), W0.copy()
         Wp[k, j] += h
@@ -385,9 +408,10 @@ def test_actuation_chain_fd():
         assert abs(fd - gb[k]) <= 1e-5 * max(abs(fd), 1e-9) + 1e-12, (k, fd, gb[k])
 
 
-def test_actuation_dot_product_complex_step():
+@pytest.mark.parametrize("name", ["actuated2d", "robot3d"])
+def test_actuation_dot_product_complex_step(name):
     """Dot-product test with a direction in the actuation table a(s, k)."""
-    sc = _small_actuated(n_keep=120, steps=6)
+    sc = _small_actuated(n_keep=120, steps=6, name=name)
     T = sc.steps
     st = _state(sc)
     rng = np.random.default_rng(4)
