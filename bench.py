@@ -11,8 +11,10 @@ timed region starts. `value` = particles x time steps x trajectories / seconds
 
 Beside it: the roofline figure of the dominant kernel (algorithmic bytes per
 launch over its mean duration, HIP events on the launch stream), the FP64 CPU
-oracle on a bounded sample of the same workload, and the batched 2D workload
-(256 scenes in one launch per step) against 256 per-scene runs.
+oracle on a bounded sample of the same workload, the batched 2D workload
+(256 scenes in one launch per step) against 256 per-scene runs, and
+open-loop controller optimisation iterations of the 3D robot (16 actuators,
+30000 particles, 512 steps).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
