@@ -8,8 +8,9 @@ pieces that are plain NumPy: the open-loop actuation signal of the 2D soft
 robot and its adjoint.
 
 Scenes are described by any object with the attributes ``dim, n_grid, bound,
-dx, dt, gravity, offsets, E, nu, vol, rho, act_id, n_act, act_strength``
-(duck-typed, so this module imports nothing from the GPU package).
+dx, dt, gravity, offsets, E, nu, vol, rho, act_id, n_act, act_strength`` and
+optionally ``model`` (0 neo-Hookean, 1 fixed-corotated; duck-typed, so this
+module imports nothing from the GPU package).
 
 State layout here: ``x (N, d), v (N, d), C (N, d, d), F (N, d, d)`` float64,
 packed particle-major into one (N, S) array with S = 2d + 2d^2.
@@ -50,6 +51,7 @@ class _Desc(ctypes.Structure):
         ("E", ctypes.POINTER(ctypes.c_double)), ("nu", ctypes.POINTER(ctypes.c_double)),
         ("vol", ctypes.POINTER(ctypes.c_double)), ("rho", ctypes.POINTER(ctypes.c_double)),
         ("act_id", ctypes.POINTER(ctypes.c_int)),
+        ("model", ctypes.c_int),
     ]
 
 
@@ -110,6 +112,7 @@ class _Bound:
             offsets=self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
             E=_dptr(self.E), nu=_dptr(self.nu), vol=_dptr(self.vol), rho=_dptr(self.rho),
             act_id=None if self.act_id is None else self.act_id.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+            model=int(getattr(sc, "model", 0) or 0),
         )
 
     @property

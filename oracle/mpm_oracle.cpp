@@ -12,7 +12,11 @@
 //     B-spline weights and APIC affine transfer, stage order clear_grid ->
 //     compute_actuation -> p2g -> grid_op -> g2p (Appendix D.1);
 //   * compressible neo-Hookean Kirchhoff stress tau = mu (F F^T - I) + lambda
-//     ln(J) I, using the initial particle volume;
+//     ln(J) I, using the initial particle volume; or (model 1) the
+//     fixed-corotated stress tau = 2 mu (F - R) F^T + lambda (J - 1) J I with R
+//     the rotation of the polar decomposition F = R S, whose derivative is the
+//     kind of hand-engineered gradient Section 3 and Appendix C describe for
+//     decompositions computed by iteration;
 //   * the adjoint of each stage written by hand: for a primal f(X) = Y the
 //     adjoint takes (X, Y*) and ACCUMULATES X* = dL/dX (Section 3 and
 //     Appendix B); the grid is recomputed inside the adjoint step instead of
@@ -62,6 +66,7 @@ struct Desc {
   const double* vol;    // [n_scenes] initial particle volume
   const double* rho;    // [n_scenes] density (particle mass = rho * vol)
   const int* act_id;    // [N] actuator column per particle, -1 = none; may be null
+  int model;            // 0: neo-Hookean, 1: fixed-corotated
 };
 
 int pow3(int d) { return d == 2 ? 9 : 27; }
@@ -173,6 +178,45 @@ void cofactor(int d, const T F[3][3], T K[3][3]) {
     }
 }
 
+// Rotation R of the polar decomposition F = R S (S symmetric positive
+// definite), for det F > 0. 2D: closed form; the rotation angle maximises
+// tr(R^T F), so (cos, sin) is the normalised (F00 + F11, F10 - F01). 3D:
+// Newton's iteration X <- (g X + (g X)^{-T}) / 2 from X = F, with the
+// determinant scaling g = det(X)^(-1/3) (Higham, 1986), until the real parts
+// stop changing. Only analytic operations touch the values, so complex-step
+// tangents pass through it.
+template <class T>
+void polar_rotation(int d, const T F[3][3], T R[3][3]) {
+  if (d == 2) {
+    T a = F[0][0] + F[1][1], b = F[1][0] - F[0][1];
+    T r = std::sqrt(a * a + b * b);
+    R[0][0] = a / r;
+    R[0][1] = -b / r;
+    R[1][0] = b / r;
+    R[1][1] = a / r;
+    return;
+  }
+  T X[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) X[a][b] = F[a][b];
+  for (int it = 0; it < 100; ++it) {
+    T K[3][3];
+    cofactor(3, X, K);
+    T J = det(3, X);
+    T g = std::pow(J, -1.0 / 3.0);
+    double change = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        T y = 0.5 * (g * X[a][b] + K[a][b] / (g * J));
+        change = std::max(change, std::abs(re(y) - re(X[a][b])));
+        X[a][b] = y;
+      }
+    if (change < 1e-15) break;
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) R[a][b] = X[a][b];
+}
+
 template <class T>
 struct Material {
   T mu, lam;
@@ -206,7 +250,7 @@ bool state_finite(const T* p, int S) {
 // A_p = m_p C_p - dt V_p kappa tau_p (momentum-exchange form of MLS-MPM).
 template <class T>
 struct P2GTerms {
-  T F[3][3], tau[3][3], A[3][3], J, lnJ, mass;
+  T F[3][3], R[3][3], tau[3][3], A[3][3], J, lnJ, mass;
   bool ok;
 };
 
@@ -228,12 +272,26 @@ int p2g_terms(const Desc& s, int sc, const T* Es, const T* act_s, int p, const P
   } else {
     t.lnJ = std::log(t.J);
   }
-  for (int a = 0; a < d; ++a)
-    for (int b = 0; b < d; ++b) {
-      T FFt = 0.0;
-      for (int c = 0; c < d; ++c) FFt += t.F[a][c] * t.F[b][c];
-      t.tau[a][b] = mat.mu * (FFt - (a == b ? 1.0 : 0.0)) + (a == b ? mat.lam * t.lnJ : T(0.0));
-    }
+  if (s.model == 1 && re(t.J) > 0.0) {
+    // tau = 2 mu (F - R) F^T + lambda (J - 1) J I
+    polar_rotation(d, t.F, t.R);
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) {
+        T FRF = 0.0;
+        for (int c = 0; c < d; ++c) FRF += (t.F[a][c] - t.R[a][c]) * t.F[b][c];
+        t.tau[a][b] = 2.0 * mat.mu * FRF + (a == b ? mat.lam * (t.J - 1.0) * t.J : T(0.0));
+      }
+  } else if (s.model == 1) {
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) t.tau[a][b] = 0.0;  // inverted: flagged above, no stress
+  } else {
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) {
+        T FFt = 0.0;
+        for (int c = 0; c < d; ++c) FFt += t.F[a][c] * t.F[b][c];
+        t.tau[a][b] = mat.mu * (FFt - (a == b ? 1.0 : 0.0)) + (a == b ? mat.lam * t.lnJ : T(0.0));
+      }
+  }
   if (act_s && s.act_id && s.act_id[p] >= 0) t.tau[1][1] += s.act_strength * act_s[s.act_id[p]];
   for (int a = 0; a < d; ++a)
     for (int b = 0; b < d; ++b) t.A[a][b] = t.mass * P.C(a, b) - s.dt * vol * kappa * t.tau[a][b];
@@ -349,6 +407,82 @@ int step_fwd(const Desc& s, const T* Es, const T* act_s, const T* in, T* out) {
   grid_update(s, grid);
   err |= g2p(s, in, grid, out);
   return err;
+}
+
+// Adjoint of the fixed-corotated stress tau = 2 mu (F F^T - R F^T) + lambda
+// (J^2 - J) I for a given tau* (accumulated into H.F) and its E-derivative
+// (into eb). Differentiating term by term:
+//   F* += 2 mu (tau* + tau*^T) F - 2 mu tau*^T R + lambda (2J - 1) tr(tau*) cof(F)
+// plus the rotation's share for R* = -2 mu tau* F. With F = R S, dR = R W,
+// W skew, and R^T dF - dF^T R = W S + S W. In 3D, W = [w]_x and
+// W S + S W = [G w]_x with G = tr(S) I - S, so <R*, dR> = a . w with a the
+// axial vector of X - X^T, X = R^T R*, and w = G^{-1} axial(R^T dF - dF^T R):
+// the share is F* += R [G^{-1} a]_x. In 2D, W = w [[0, -1], [1, 0]], w =
+// (Y10 - Y01) / tr(S) with Y = R^T dF, and the share is R [[0, -c], [c, 0]]
+// with c = (X10 - X01) / tr(S).
+void corotated_adjoint(int d, const P2GTerms<double>& t, const Material<double>& mat, const double tb[3][3],
+                       PView<double>& H, double& eb) {
+  const double J = t.J;
+  double cof[3][3];
+  cofactor(d, t.F, cof);
+  double tr = 0.0;
+  for (int a = 0; a < d; ++a) tr += tb[a][a];
+  double Fbar[3][3] = {};
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      double v = 0.0;
+      for (int c = 0; c < d; ++c) v += (tb[a][c] + tb[c][a]) * t.F[c][b] - tb[c][a] * t.R[c][b];
+      Fbar[a][b] = 2.0 * mat.mu * v + mat.lam * (2.0 * J - 1.0) * tr * cof[a][b];
+    }
+  // R* = -2 mu tau* F, X = R^T R*, S = R^T F.
+  double Rbar[3][3] = {}, X[3][3] = {}, S[3][3] = {};
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b)
+      for (int c = 0; c < d; ++c) Rbar[a][b] += -2.0 * mat.mu * tb[a][c] * t.F[c][b];
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b)
+      for (int c = 0; c < d; ++c) {
+        X[a][b] += t.R[c][a] * Rbar[c][b];
+        S[a][b] += t.R[c][a] * t.F[c][b];
+      }
+  double trS = 0.0;
+  for (int a = 0; a < d; ++a) trS += S[a][a];
+  double Wc[3][3] = {};
+  if (d == 2) {
+    double c = (X[1][0] - X[0][1]) / trS;
+    Wc[0][1] = -c;
+    Wc[1][0] = c;
+  } else {
+    double av[3] = {X[2][1] - X[1][2], X[0][2] - X[2][0], X[1][0] - X[0][1]};
+    double G[3][3], Gc[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) G[a][b] = (a == b ? trS : 0.0) - S[a][b];
+    cofactor(3, G, Gc);  // G^{-1} = cof(G)^T / det G; G is symmetric
+    double dG = det(3, G);
+    double c[3];
+    for (int a = 0; a < 3; ++a) {
+      c[a] = 0.0;
+      for (int b = 0; b < 3; ++b) c[a] += Gc[b][a] * av[b];
+      c[a] /= dG;
+    }
+    Wc[0][1] = -c[2]; Wc[0][2] = c[1];
+    Wc[1][0] = c[2];  Wc[1][2] = -c[0];
+    Wc[2][0] = -c[1]; Wc[2][1] = c[0];
+  }
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      double v = 0.0;
+      for (int c = 0; c < d; ++c) v += t.R[a][c] * Wc[c][b];
+      H.F(a, b) += Fbar[a][b] + v;
+    }
+  // dtau/dE = 2 (F - R) F^T dmu/dE + (J - 1) J I dlambda/dE.
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      double FRF = 0.0;
+      for (int c = 0; c < d; ++c) FRF += (t.F[a][c] - t.R[a][c]) * t.F[b][c];
+      double dtau = 2.0 * mat.dmu_dE * FRF + (a == b ? mat.dlam_dE * (J - 1.0) * J : 0.0);
+      eb += tb[a][b] * dtau;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -492,26 +626,30 @@ int step_bwd(const Desc& s, const double* act_s, const double* in, const double*
         taubar[a][b] = -s.dt * vol * kappa * Abar[a][b];
       }
     for (int a = 0; a < d; ++a) tr += taubar[a][a];
-    // tau = mu (F F^T - I) + lambda ln J I
-    //  => F* += mu (tau* + tau*^T) F + lambda tr(tau*) F^{-T}.
     double cof[3][3];
     cofactor(d, t.F, cof);
-    for (int a = 0; a < d; ++a)
-      for (int b = 0; b < d; ++b) {
-        double sym = 0.0;
-        for (int c = 0; c < d; ++c) sym += (taubar[a][c] + taubar[c][a]) * t.F[c][b];
-        double Finv_t = (re(t.J) > 0.0) ? cof[a][b] / t.J : 0.0;
-        H.F(a, b) += mat.mu * sym + mat.lam * tr * Finv_t;
-      }
-    // dtau/dE = (F F^T - I) dmu/dE + ln J dlambda/dE I.
     double eb = 0.0;
-    for (int a = 0; a < d; ++a)
-      for (int b = 0; b < d; ++b) {
-        double FFt = 0.0;
-        for (int c = 0; c < d; ++c) FFt += t.F[a][c] * t.F[b][c];
-        double dtau = mat.dmu_dE * (FFt - (a == b ? 1.0 : 0.0)) + (a == b ? mat.dlam_dE * t.lnJ : 0.0);
-        eb += taubar[a][b] * dtau;
-      }
+    if (s.model == 1) {
+      if (re(t.J) > 0.0) corotated_adjoint(d, t, mat, taubar, H, eb);
+    } else {
+      // tau = mu (F F^T - I) + lambda ln J I
+      //  => F* += mu (tau* + tau*^T) F + lambda tr(tau*) F^{-T}.
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+          double sym = 0.0;
+          for (int c = 0; c < d; ++c) sym += (taubar[a][c] + taubar[c][a]) * t.F[c][b];
+          double Finv_t = (re(t.J) > 0.0) ? cof[a][b] / t.J : 0.0;
+          H.F(a, b) += mat.mu * sym + mat.lam * tr * Finv_t;
+        }
+      // dtau/dE = (F F^T - I) dmu/dE + ln J dlambda/dE I.
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+          double FFt = 0.0;
+          for (int c = 0; c < d; ++c) FFt += t.F[a][c] * t.F[b][c];
+          double dtau = mat.dmu_dE * (FFt - (a == b ? 1.0 : 0.0)) + (a == b ? mat.dlam_dE * t.lnJ : 0.0);
+          eb += taubar[a][b] * dtau;
+        }
+    }
     if (gE) gE[sc] += eb;
     if (gact && act_s && s.act_id && s.act_id[p] >= 0) gact[s.act_id[p]] += s.act_strength * taubar[1][1];
   }
@@ -532,6 +670,7 @@ struct orc_desc {
   const double* vol;
   const double* rho;
   const int* act_id;
+  int model;
 };
 
 static Desc to_desc(const orc_desc* o) {
@@ -539,6 +678,7 @@ static Desc to_desc(const orc_desc* o) {
   s.dim = o->dim; s.n_grid = o->n_grid; s.bound = o->bound; s.n_scenes = o->n_scenes; s.n_act = o->n_act;
   s.dx = o->dx; s.dt = o->dt; s.gravity = o->gravity; s.act_strength = o->act_strength;
   s.offsets = o->offsets; s.E = o->E; s.nu = o->nu; s.vol = o->vol; s.rho = o->rho; s.act_id = o->act_id;
+  s.model = o->model;
   return s;
 }
 

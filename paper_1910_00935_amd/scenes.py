@@ -62,6 +62,7 @@ class Scene:
     act_W: Optional[np.ndarray] = None    # float32 (n_act, n_sin)
     act_b: Optional[np.ndarray] = None    # float32 (n_act,)
     act_omega: float = 0.0
+    model: int = 0                        # 0: neo-Hookean, 1: fixed-corotated
     meta: dict = field(default_factory=dict)
 
     @property

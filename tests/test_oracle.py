@@ -136,6 +136,68 @@ def test_stress_frame_indifference():
     np.testing.assert_allclose(tau_of(R @ F), R @ tau_of(F) @ R.T, rtol=1e-11, atol=1e-12)
 
 
+def _rotation(dim, angles):
+    if dim == 2:
+        c, s_ = np.cos(angles[0]), np.sin(angles[0])
+        return np.array([[c, -s_], [s_, c]])
+    R = np.eye(3)
+    for ax, th in enumerate(angles):
+        c, s_ = np.cos(th), np.sin(th)
+        i, j = [a for a in range(3) if a != ax]
+        G = np.eye(3)
+        G[i, i], G[i, j], G[j, i], G[j, j] = c, -s_, s_, c
+        R = R @ G
+    return R
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_corotated_stress_closed_form(dim):
+    """Fixed-corotated stress of F = R0 S0 with a known rotation R0 and a
+    symmetric positive definite S0 (so R0 is the polar rotation), read back
+    through the grid's second moment: tau = 2 mu (F - R0) F^T + lambda (J - 1) J I."""
+    n = 16
+    dx = 1.0 / n
+    R0 = _rotation(dim, [0.4, -0.3, 0.25][: 1 if dim == 2 else 3])
+    Q = _rotation(dim, [0.7, 0.2, -0.5][: 1 if dim == 2 else 3])
+    S0 = Q @ np.diag([1.15, 0.9, 1.05][:dim]) @ Q.T
+    F = R0 @ S0
+    x = np.array([7.3, 8.6, 7.9][:dim]) * dx
+    E, nu = 10.0, 0.25
+    sc = replace(_one_particle(dim, x, F=F, n=n, E=E, nu=nu), model=1)
+    gp, _, err = orc.grid(sc, _state(sc))
+    assert err == 0
+    delta = _node_coords(n, dim) * dx - x
+    tau = -(gp[0, :, 1:].T @ delta) / (sc.dt * sc.vol[0])
+    mu = E / (2 * (1 + nu))
+    lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+    J = np.linalg.det(F)
+    expect = 2 * mu * (F - R0) @ F.T + lam * (J - 1) * J * np.eye(dim)
+    np.testing.assert_allclose(tau, expect, rtol=1e-11, atol=1e-12)
+    # A pure rotation carries no stress.
+    sc_r = replace(_one_particle(dim, x, F=R0, n=n, E=E, nu=nu), model=1)
+    gp_r, _, _ = orc.grid(sc_r, _state(sc_r))
+    tau_r = -(gp_r[0, :, 1:].T @ delta) / (sc_r.dt * sc_r.vol[0])
+    np.testing.assert_allclose(tau_r, 0.0, atol=1e-10)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_corotated_frame_indifference(dim):
+    """tau(Q F) = Q tau(F) Q^T for the fixed-corotated stress of a generic F."""
+    n = 16
+    dx = 1.0 / n
+    x = np.array([7.4, 8.2, 7.7][:dim]) * dx
+    F = np.eye(dim) + 0.08 * np.random.default_rng(3).normal(size=(dim, dim))
+    Q = _rotation(dim, [0.3, 0.5, -0.2][: 1 if dim == 2 else 3])
+
+    def tau_of(Fm):
+        sc = replace(_one_particle(dim, x, F=Fm, n=n), model=1)
+        gp, _, _ = orc.grid(sc, _state(sc))
+        delta = _node_coords(n, dim) * dx - x
+        return -(gp[0, :, 1:].T @ delta) / (sc.dt * sc.vol[0])
+
+    np.testing.assert_allclose(tau_of(Q @ F), Q @ tau_of(F) @ Q.T, rtol=1e-10, atol=1e-11)
+
+
 # ---------------------------------------------------------------------------
 # Conservation and symmetry of whole steps.
 # ---------------------------------------------------------------------------
@@ -212,12 +274,15 @@ def test_mirror_symmetry(dim, axis):
 # The adjoint: dot-product test against complex-step tangents, finite
 # differences, checkpoint equivalence, batch independence.
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("model", [0, 1])
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("T", [1, 12])
-def test_dot_product_complex_step(dim, T):
+def test_dot_product_complex_step(dim, T, model):
     """<J u, w> (complex-step tangent of the forward) equals <u, J^T w> (the
-    hand-written reverse pass) for random u (state and E) and w."""
-    sc = scenes.fd8(dim, steps=T)
+    hand-written reverse pass) for random u (state and E) and w; model 1 runs
+    the fixed-corotated stress, whose reverse differentiates the polar
+    decomposition by hand."""
+    sc = replace(scenes.fd8(dim, steps=T), model=model)
     st = _state(sc)
     rng = np.random.default_rng(7 + dim + T)
     u = rng.normal(size=st.shape)
@@ -243,12 +308,13 @@ def test_dot_product_complex_step(dim, T):
         assert abs(l2 - r2) <= 1e-11 * max(abs(l2), 1.0), (blk, l2, r2)
 
 
+@pytest.mark.parametrize("model", [0, 1])
 @pytest.mark.parametrize("dim", [2, 3])
-def test_finite_differences_fd8(dim):
+def test_finite_differences_fd8(dim, model):
     """Central differences (h = 1e-6) of a random linear functional of the state
     after 16 steps, with respect to every input component and E, against the
     reverse pass: relative error <= 1e-6."""
-    sc = scenes.fd8(dim, steps=16)
+    sc = replace(scenes.fd8(dim, steps=16), model=model)
     st = _state(sc)
     T = sc.steps
     rng = np.random.default_rng(11)
