@@ -313,6 +313,37 @@ def run_batched(args, torch, rt, scenes, n_scenes=256, steps=256):
             "knobs_batched": knobs, "knobs_per_scene": knobs_one}
 
 
+def run_corotated(args, torch, rt, scenes, knobs):
+    """The 3D workload with the fixed-corotated stress (polar decomposition in
+    every stress evaluation and its hand-written gradient), same launch
+    configuration as the headline run."""
+    from dataclasses import replace
+    sc = replace(scenes.elastic3d(), model=1)
+    T, N = sc.steps, sc.n_particles
+    sim = rt.Simulator.for_scene(sc, knobs=knobs)
+    params = rt.params_for_scene(sc)
+    init = rt.state_for_scene(sc)
+    tape = sim.tape(T, 0)
+    final, seed, grad = rt.State.empty(3, N), rt.State.empty(3, N), rt.State.zeros(3, N)
+
+    def step():
+        tape.forward(params, init, final)
+        sim.loss_mean(final, sc.loss_axis, sc.loss_sign, seed)
+        tape.backward(params, seed, grad)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    if sim.check_errors():
+        raise RuntimeError("corotated run: simulation error flags set")
+    return {"workload": "elastic3d workload with the fixed-corotated stress", "knobs": knobs,
+            "particle_steps_per_s": N * T * args.steps / secs, "ms_per_trajectory": secs * 1e3 / args.steps}
+
+
 def run_robot3d(args, torch, rt, scenes, iters=3):
     """The 3D actuated robot (16 actuators, 30000 particles, 512 steps): open-loop
     controller optimisation iterations (actuation signal, tape forward, loss,
@@ -417,6 +448,8 @@ def main():
     if not args.no_robot:
         print("[bench] 3D robot controller optimisation", flush=True)
         out["robot3d"] = run_robot3d(args, torch, rt, scenes)
+        print("[bench] fixed-corotated model", flush=True)
+        out["elastic3d_corotated"] = run_corotated(args, torch, rt, scenes, elastic3d["knobs"])
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", flush=True)
         out["cpu_baseline"] = run_cpu_baseline(args.cpu_sample_steps)

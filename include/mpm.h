@@ -77,7 +77,16 @@ typedef struct mpm_tape mpm_tape;
  *                 N = scene_offsets[n_scenes] >= 1.
  *   n_actuators   actuator columns (0..16); act_strength sigma_a multiplies
  *                 the actuation a_k(s) added to the yy Kirchhoff stress.
- *   flags         reserved, 0. */
+ *   flags         0 or MPM_MODEL_COROTATED; other bits give MPM_E_ARG.
+ *
+ * Constitutive model (Kirchhoff stress tau, initial particle volume): by
+ * default compressible neo-Hookean, tau = mu (F F^T - I) + lambda ln(J) I.
+ * With MPM_MODEL_COROTATED, fixed-corotated, tau = 2 mu (F - R) F^T +
+ * lambda (J - 1) J I with R the rotation of the polar decomposition F = R S;
+ * its reverse pass differentiates the decomposition by hand (the custom
+ * gradients of Section 3 and Appendix C). An inverted F (J <= 0) sets
+ * MPM_FLAG_INVERTED and, for this model, carries no stress. */
+#define MPM_MODEL_COROTATED 1u
 typedef struct {
   int32_t dim;
   int32_t n_grid;
@@ -101,7 +110,7 @@ typedef struct {
 } mpm_state;
 
 /* Material and actuation parameters (device pointers).
- *   E, nu    [n_scenes] Young's modulus and Poisson ratio, neo-Hookean with
+ *   E, nu    [n_scenes] Young's modulus and Poisson ratio; Lame parameters
  *            mu = E / (2 (1 + nu)), lambda = E nu / ((1 + nu)(1 - 2 nu)).
  *   vol      [n_scenes] initial particle volume V_p.
  *   rho      [n_scenes] density; particle mass m_p = rho * vol.

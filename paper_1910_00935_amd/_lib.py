@@ -24,6 +24,7 @@ MPM_FLAG_DOMAIN = 1
 MPM_FLAG_INVERTED = 2
 MPM_FLAG_NONFINITE = 4
 MPM_LOSS_MEAN_POS = 0
+MPM_MODEL_COROTATED = 1
 MPM_KERNEL_FWD = 0
 MPM_KERNEL_BWD = 1
 

@@ -4,7 +4,10 @@
 // stage order of Appendix D.1): quadratic B-spline weights on the 3^d nodes
 // base .. base+2 with base = floor(x/dx - 1/2); APIC/MLS affine momentum
 // transfer with kappa = 4/dx^2; compressible neo-Hookean Kirchhoff stress
-// tau = mu (F F^T - I) + lambda ln(J) I evaluated with the initial volume;
+// tau = mu (F F^T - I) + lambda ln(J) I evaluated with the initial volume, or
+// the fixed-corotated tau = 2 mu (F - R) F^T + lambda (J - 1) J I with R the
+// polar rotation of F and a hand-written gradient of the decomposition (the
+// custom gradients of Section 3 and Appendix C);
 // grid update v = P/m + dt g e_1 on interior nodes with mass (sticky band of
 // `bound` nodes, zero elsewhere); grid-to-particle gather of v and
 // C = kappa sum w v delta^T, x' = x + dt v', F' = (I + dt C') F.
@@ -183,6 +186,48 @@ __device__ __forceinline__ void cofactor(const float (&F)[D][D], float (&K)[D][D
   }
 }
 
+// Rotation R of the polar decomposition F = R S (S symmetric positive
+// definite), for det F > 0. 2D: the rotation angle maximises tr(R^T F), so
+// (cos, sin) is the normalised (F00 + F11, F10 - F01). 3D: kPolarIters steps
+// of Newton's iteration X <- (g X + X^{-T} / g) / 2 from X = F, with the
+// determinant scaling g = det(X)^(-1/3) (Higham, 1986); each step roughly
+// squares the distance to R, so strains of tens of percent reach FP32
+// precision well within the fixed count.
+constexpr int kPolarIters = 6;
+
+template <int D>
+__device__ __forceinline__ void polar_rotation(const float (&F)[D][D], float (&R)[D][D]) {
+  if constexpr (D == 2) {
+    const float a = F[0][0] + F[1][1], b = F[1][0] - F[0][1];
+    const float inv = 1.0f / sqrtf(a * a + b * b);
+    R[0][0] = a * inv;
+    R[0][1] = -b * inv;
+    R[1][0] = b * inv;
+    R[1][1] = a * inv;
+  } else {
+    float X[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) X[a][b] = F[a][b];
+    for (int it = 0; it < kPolarIters; ++it) {
+      float K[3][3];
+      cofactor<3>(X, K);
+      const float J = X[0][0] * K[0][0] + X[0][1] * K[0][1] + X[0][2] * K[0][2];
+      const float g = 1.0f / cbrtf(J);
+      const float h = 1.0f / (g * J);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) X[a][b] = 0.5f * (g * X[a][b] + h * K[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) R[a][b] = X[a][b];
+  }
+}
+
 struct SceneParams {
   float mass, vol, mu, lam, dmu_dE, dlam_dE;
 };
@@ -228,6 +273,123 @@ __device__ __forceinline__ void affine(const PState<D>& p, const SceneParams& sp
     }
 }
 
+
+// Fixed-corotated Kirchhoff stress tau = 2 mu (F - R) F^T + lambda (J - 1) J I
+// (R the polar rotation of F) and the affine matrix A = m C - dt V kappa tau.
+// An inverted F (J <= 0) raises the error bit and carries no stress. Also
+// returns R for the adjoint.
+template <int D>
+__device__ __forceinline__ void affine_corotated(const PState<D>& p, const SceneParams& sp, float act_tau, float dt,
+                                                 float kappa, float (&A)[D][D], float (&R)[D][D], float& J,
+                                                 unsigned& err) {
+  J = det<D>(p.F);
+  const bool ok = J > 0.0f;
+  if (!ok) err |= kErrInverted;
+  polar_rotation<D>(p.F, R);
+  const float k = dt * sp.vol * kappa;
+  const float vol_term = ok ? sp.lam * (J - 1.0f) * J : 0.0f;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float s = 0.0f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) s += (p.F[a][c] - R[a][c]) * p.F[b][c];
+      float tau = ok ? 2.0f * sp.mu * s + (a == b ? vol_term : 0.0f) : 0.0f;
+      if (a == 1 && b == 1) tau += act_tau;
+      A[a][b] = sp.mass * p.C[a][b] - k * tau;
+    }
+}
+
+// Adjoint of the fixed-corotated stress: given tb = dL/dtau, ADDS dL/dF into
+// gF and returns dL/dE through tau. Term by term,
+//   F* = 2 mu [(tb + tb^T) F - tb^T R] + lambda (2J - 1) tr(tb) cof(F) + (rotation share),
+// and the rotation's share for R* = -2 mu tb F follows from F = R S: dR = R W
+// with W skew and R^T dF - dF^T R = W S + S W. In 3D, W = [w]_x and W S + S W
+// = [(tr(S) I - S) w]_x, which gives the share R [c]_x with c = (tr(S) I -
+// S)^{-1} a, a the axial vector of X - X^T, X = R^T R*. In 2D the share is
+// R [[0, -c], [c, 0]] with c = (X10 - X01) / tr(S).
+template <int D>
+__device__ __forceinline__ float corotated_adjoint(const PState<D>& p, const SceneParams& sp, const float (&R)[D][D],
+                                                   float J, const float (&tb)[D][D], float (&gF)[D][D]) {
+  if (!(J > 0.0f)) return 0.0f;
+  float K[D][D];
+  cofactor<D>(p.F, K);
+  float tr = 0.0f;
+#pragma unroll
+  for (int a = 0; a < D; ++a) tr += tb[a][a];
+  const float vol_c = sp.lam * (2.0f * J - 1.0f) * tr;
+  float X[D][D], S[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float v = 0.0f, rb = 0.0f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        v += (tb[a][c] + tb[c][a]) * p.F[c][b] - tb[c][a] * R[c][b];
+        rb += tb[a][c] * p.F[c][b];
+      }
+      gF[a][b] += 2.0f * sp.mu * v + vol_c * K[a][b];
+      X[a][b] = -2.0f * sp.mu * rb;  // R* for now; turned into R^T R* below
+    }
+  float Xt[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float x = 0.0f, sv = 0.0f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        x += R[c][a] * X[c][b];
+        sv += R[c][a] * p.F[c][b];
+      }
+      Xt[a][b] = x;
+      S[a][b] = sv;
+    }
+  float trS = 0.0f;
+#pragma unroll
+  for (int a = 0; a < D; ++a) trS += S[a][a];
+  float W[D][D] = {};
+  if constexpr (D == 2) {
+    const float c = (Xt[1][0] - Xt[0][1]) / trS;
+    W[0][1] = -c;
+    W[1][0] = c;
+  } else {
+    const float av[3] = {Xt[2][1] - Xt[1][2], Xt[0][2] - Xt[2][0], Xt[1][0] - Xt[0][1]};
+    float G[3][3], Gc[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) G[a][b] = (a == b ? trS : 0.0f) - 0.5f * (S[a][b] + S[b][a]);
+    cofactor<3>(G, Gc);
+    const float inv_det = 1.0f / (G[0][0] * Gc[0][0] + G[0][1] * Gc[0][1] + G[0][2] * Gc[0][2]);
+    float c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c[a] = (Gc[a][0] * av[0] + Gc[a][1] * av[1] + Gc[a][2] * av[2]) * inv_det;
+    W[0][1] = -c[2];
+    W[0][2] = c[1];
+    W[1][0] = c[2];
+    W[1][2] = -c[0];
+    W[2][0] = -c[1];
+    W[2][1] = c[0];
+  }
+  float eb = 0.0f;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float v = 0.0f, frf = 0.0f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        v += R[a][c] * W[c][b];
+        frf += (p.F[a][c] - R[a][c]) * p.F[b][c];
+      }
+      gF[a][b] += v;
+      eb += tb[a][b] * (2.0f * sp.dmu_dE * frf + (a == b ? sp.dlam_dE * (J - 1.0f) * J : 0.0f));
+    }
+  return eb;
+}
 
 __device__ __forceinline__ bool interior1(int i, int n, int bound) { return i >= bound && i < n - bound; }
 

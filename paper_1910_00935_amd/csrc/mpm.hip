@@ -79,6 +79,7 @@ struct mpm_ctx {
   int lanes = 1;
   int graph = 1;
   int part = 1;      // 1: workgroups aligned to the Morton cell hierarchy (rebuilt at each sort)
+  int model = 0;     // constitutive model: 0 neo-Hookean, 1 fixed-corotated (MPM_MODEL_COROTATED)
   int n_blocks = 0;  // workgroups per particle pass for the current block and lanes
   int n_plain = 0;   // workgroups of the plain partition
   long blocks_cap = 0;
@@ -336,7 +337,10 @@ mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& args, hipStream_t st) {
   a.k.threads = c.block;
   a.k.clear_per_role = c.part ? c.n_plain : c.n_blocks;
   a.k.groups = a.k.clear_per_role;
-  hipLaunchKernelGGL((mpm::k_fwd<D, LPP>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
+  if (c.model == 1)
+    hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 1>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
+  else
+    hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 0>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
   LAUNCH_TRY();
   return MPM_OK;
 }
@@ -349,7 +353,10 @@ mpm_status launch_bwd(const mpm_ctx& c, const BwdArgs& args, hipStream_t st) {
   a.k.threads = c.block;
   a.k.clear_per_role = c.part ? c.n_plain : c.n_blocks;
   a.k.groups = (args.split_c ? 2 : 1) * a.k.clear_per_role;
-  hipLaunchKernelGGL((mpm::k_bwd<D, LPP>), dim3(nb), dim3(c.block), 0, st, a);
+  if (c.model == 1)
+    hipLaunchKernelGGL((mpm::k_bwd<D, LPP, 1>), dim3(nb), dim3(c.block), 0, st, a);
+  else
+    hipLaunchKernelGGL((mpm::k_bwd<D, LPP, 0>), dim3(nb), dim3(c.block), 0, st, a);
   LAUNCH_TRY();
   return MPM_OK;
 }
@@ -589,6 +596,7 @@ mpm_status mpm_init(const mpm_desc* desc, mpm_ctx** out) {
   if (!(d.dx > 0.0f) || !(d.dt > 0.0f)) return MPM_E_ARG;
   if (d.n_scenes < 1 || !d.scene_offsets) return MPM_E_ARG;
   if (d.n_actuators < 0 || d.n_actuators > mpm::kMaxAct) return MPM_E_ARG;
+  if (d.flags & ~uint32_t(MPM_MODEL_COROTATED)) return MPM_E_ARG;
   if (d.scene_offsets[0] != 0) return MPM_E_ARG;
   for (int k = 0; k < d.n_scenes; ++k)
     if (d.scene_offsets[k + 1] < d.scene_offsets[k]) return MPM_E_ARG;
@@ -605,6 +613,7 @@ mpm_status mpm_init(const mpm_desc* desc, mpm_ctx** out) {
   c->bound = d.bound;
   c->ns = d.n_scenes;
   c->n_act = d.n_actuators;
+  c->model = (d.flags & MPM_MODEL_COROTATED) ? 1 : 0;
   c->N = int(Nl);
   c->Np = int(align_up(size_t(Nl), 64));
   c->S = 2 * d.dim + 2 * d.dim * d.dim;

@@ -1194,7 +1194,7 @@ __device__ __forceinline__ int actuator_of(const StepConsts& k, const float* act
 // Scatter of one state into `grid` with an optional LDS tile (all threads
 // call). The fixed-point tile must already be zero over its first D + 1
 // components (zero_tile64).
-template <int D, int LPP>
+template <int D, int LPP, int M>
 __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i, int sc, bool one_scene, int sub,
                                           const PState<D>& p, const float* act_row, float4* grid,
                                           long long* tile, BlockRed& rd, unsigned& err, int4* box_out, int wg) {
@@ -1209,8 +1209,13 @@ __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i,
     const SceneParams sp = scene_params(k.E, k.nu, k.vol, k.rho, sc);
     float act_tau;
     actuator_of<D>(k, act_row, i, act_tau);
-    float FFtI[D][D], lnJ, J;
-    affine<D>(p, sp, act_tau, k.dt, k.kappa, A, FFtI, lnJ, J, err);
+    if constexpr (M == 1) {
+      float R[D][D], J;
+      affine_corotated<D>(p, sp, act_tau, k.dt, k.kappa, A, R, J, err);
+    } else {
+      float FFtI[D][D], lnJ, J;
+      affine<D>(p, sp, act_tau, k.dt, k.kappa, A, FFtI, lnJ, J, err);
+    }
 #pragma unroll
     for (int a = 0; a < D; ++a) mv[a] = sp.mass * p.v[a];
     mass = sp.mass;
@@ -1285,7 +1290,8 @@ struct LaneMap {
   }
 };
 
-template <int D, int LPP>
+// M: constitutive model (0 neo-Hookean, 1 fixed-corotated).
+template <int D, int LPP, int M>
 __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   constexpr int S0 = (LPP == 4) ? 1 : (LPP == 2 ? 2 : 3);
   __shared__ long long tile64[(D + 1) * kTileCap<D>];  // P2G scatter tile (fixed point)
@@ -1343,7 +1349,7 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
     clear_jobs_run<D>(cj, c0, c1, k, rank);
   }
   if (a.do_p2g)
-    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_row, a.grid_out, tile64, rd, err, a.box_out,
+    p2g_phase<D, LPP, M>(k, live, i, sc, one_scene, sub, p, a.act_row, a.grid_out, tile64, rd, err, a.box_out,
                       int(blockIdx.x));
   if (err) atomicOr(k.err, err);
 }
@@ -1363,7 +1369,7 @@ __device__ __forceinline__ void wave_add_keyed(bool live, int key, double val, d
   }
 }
 
-template <int D, int LPP>
+template <int D, int LPP, int M>
 __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   constexpr int S0 = (LPP == 4) ? 1 : (LPP == 2 ? 2 : 3);
   __shared__ float tA[(D + 1) * kTileCap<D>];      // phase A: adjoint tile (P*, m*)
@@ -1402,7 +1408,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     PState<D> p;
     if (live) load_state<D>(a.stC, i, p);
     clear_jobs_run<D>(cj, c0, c1, k, rank);
-    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
+    p2g_phase<D, LPP, M>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
     if (err) atomicOr(k.err, err);
     return;
   }
@@ -1473,9 +1479,12 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
       const SceneParams sp = scene_params(k.E, k.nu, k.vol, k.rho, sc);
       float act_tau;
       aid = actuator_of<D>(k, a.act_rowA, i, act_tau);
-      float A[D][D], FFtI[D][D], lnJ, J;
+      float A[D][D], FFtI[D][D], lnJ, J, R[D][D];
       unsigned dummy = 0;
-      affine<D>(p, sp, act_tau, k.dt, k.kappa, A, FFtI, lnJ, J, dummy);
+      if constexpr (M == 1)
+        affine_corotated<D>(p, sp, act_tau, k.dt, k.kappa, A, R, J, dummy);
+      else
+        affine<D>(p, sp, act_tau, k.dt, k.kappa, A, FFtI, lnJ, J, dummy);
       float mv[D];
 #pragma unroll
       for (int c = 0; c < D; ++c) mv[c] = sp.mass * p.v[c];
@@ -1497,23 +1506,27 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
         }
         tr += tb[c][c];
       }
-      // tau = mu (F F^T - I) + lambda ln J I:
-      // F* += mu (tau* + tau*^T) F + lambda tr(tau*) F^{-T}.
-      float K[D][D];
-      cofactor<D>(p.F, K);
-      const float lam_tr_invJ = (J > 0.0f) ? sp.lam * tr / J : 0.0f;
-      float ebf = 0.0f;
+      if constexpr (M == 1) {
+        eb = corotated_adjoint<D>(p, sp, R, J, tb, gF);
+      } else {
+        // tau = mu (F F^T - I) + lambda ln J I:
+        // F* += mu (tau* + tau*^T) F + lambda tr(tau*) F^{-T}.
+        float K[D][D];
+        cofactor<D>(p.F, K);
+        const float lam_tr_invJ = (J > 0.0f) ? sp.lam * tr / J : 0.0f;
+        float ebf = 0.0f;
 #pragma unroll
-      for (int c = 0; c < D; ++c)
+        for (int c = 0; c < D; ++c)
 #pragma unroll
-        for (int b = 0; b < D; ++b) {
-          float sym = 0.0f;
+          for (int b = 0; b < D; ++b) {
+            float sym = 0.0f;
 #pragma unroll
-          for (int e = 0; e < D; ++e) sym += (tb[c][e] + tb[e][c]) * p.F[e][b];
-          gF[c][b] += sp.mu * sym + lam_tr_invJ * K[c][b];
-          ebf += tb[c][b] * (sp.dmu_dE * FFtI[c][b] + (c == b ? sp.dlam_dE * lnJ : 0.0f));
-        }
-      eb = ebf;
+            for (int e = 0; e < D; ++e) sym += (tb[c][e] + tb[e][c]) * p.F[e][b];
+            gF[c][b] += sp.mu * sym + lam_tr_invJ * K[c][b];
+            ebf += tb[c][b] * (sp.dmu_dE * FFtI[c][b] + (c == b ? sp.dlam_dE * lnJ : 0.0f));
+          }
+        eb = ebf;
+      }
       actb = double(k.act_strength) * tb[1][1];
     }
   }
@@ -1660,7 +1673,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     if (live) load_state<D>(a.stC, i, p);
     __syncthreads();  // every thread is done with the scatter tile of phase B
     if (k.lds) zero_tile64<D, D + 1>(tS, k.threads);
-    p2g_phase<D, LPP>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
+    p2g_phase<D, LPP, M>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
   }
   if (err) atomicOr(k.err, err);
 }

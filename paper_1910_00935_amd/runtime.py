@@ -105,7 +105,7 @@ class Simulator:
     """One context: a description (grid, time step, scenes) plus bound workspace."""
 
     def __init__(self, dim, n_grid, dx, dt, scene_offsets, gravity=-9.8, bound=3, n_actuators=0,
-                 act_strength=0.0, device="cuda", knobs: Optional[dict] = None):
+                 act_strength=0.0, device="cuda", knobs: Optional[dict] = None, model: int = 0):
         self.dim, self.n_grid, self.dx, self.dt = int(dim), int(n_grid), float(dx), float(dt)
         self.offsets = np.ascontiguousarray(scene_offsets, dtype=np.int32)
         self.n_scenes = len(self.offsets) - 1
@@ -114,7 +114,8 @@ class Simulator:
         self.device = device
         self._off_c = self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         desc = L.mpm_desc(self.dim, self.n_grid, int(bound), self.dx, self.dt, float(gravity), self.n_scenes,
-                          self._off_c, self.n_act, float(act_strength), 0)
+                          self._off_c, self.n_act, float(act_strength),
+                          L.MPM_MODEL_COROTATED if model == 1 else 0)
         self.ctx = L.mpm_init(desc)
         self.workspace = _dev_bytes(L.mpm_workspace_bytes(self.ctx), device)
         L.mpm_bind_workspace(self.ctx, self.workspace.data_ptr(), self.workspace.numel())
@@ -125,7 +126,7 @@ class Simulator:
     def for_scene(scene, device="cuda", knobs=None) -> "Simulator":
         return Simulator(scene.dim, scene.n_grid, scene.dx, scene.dt, scene.offsets, gravity=scene.gravity,
                          bound=scene.bound, n_actuators=scene.n_act, act_strength=scene.act_strength,
-                         device=device, knobs=knobs)
+                         device=device, knobs=knobs, model=int(getattr(scene, "model", 0) or 0))
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)

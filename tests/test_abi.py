@@ -31,10 +31,10 @@ def test_library_exports_every_declared_symbol():
     assert sorted(L._SIGNATURES) == names
 
 
-def _desc(dim=3, n=64, ns=1, N=1000, bound=3, n_act=0, offsets=None):
+def _desc(dim=3, n=64, ns=1, N=1000, bound=3, n_act=0, offsets=None, flags=0):
     off = np.array(offsets if offsets is not None else np.linspace(0, N, ns + 1).astype(int), np.int32)
     d = L.mpm_desc(dim, n, bound, 1.0 / n, 1e-3, -9.8, len(off) - 1,
-                   off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_act, 0.0, 0)
+                   off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_act, 0.0, flags)
     return d, off
 
 
@@ -57,6 +57,8 @@ def test_init_validates_description():
     assert _init_status(offsets=[3, 10]) == L.MPM_E_ARG     # offsets[0] != 0
     assert _init_status(offsets=[0, 0]) == L.MPM_E_ARG      # no particles
     assert _init_status(n_act=17) == L.MPM_E_ARG
+    assert _init_status(flags=L.MPM_MODEL_COROTATED) == L.MPM_OK
+    assert _init_status(flags=2) == L.MPM_E_ARG
     h = ctypes.c_void_p()
     assert L.lib().mpm_init(None, ctypes.byref(h)) == L.MPM_E_ARG
 

@@ -8,7 +8,7 @@ import oracle as orc
 from paper_1910_00935_amd import runtime as rt
 from paper_1910_00935_amd import scenes
 
-from parity import act_table, compare, gpu_run, log, oracle_run, random_seed, rel
+from parity import act_table, compare, cos, gpu_run, log, oracle_run, random_seed, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -126,4 +126,22 @@ def test_robot3d_partitions(part):
     g = gpu_run(sc, 48, act=act, seed=w, knobs={"block": 256, "part": part})
     o = oracle_run(sc, 48, act=act, seed=w)
     compare(f"robot3d@48 part={part}", sc, g, o, grads=("x", "v", "C", "F"))
+
+
+@pytest.mark.parametrize("name,T,knobs", [("deform2d", 24, {"lanes": 1}), ("deform2d", 24, {"lanes": 4}),
+                                          ("elastic3d", 32, {"block": 256}),
+                                          ("robot3d", 32, {"block": 128, "lanes": 2})])
+def test_corotated_parity(name, T, knobs):
+    """Fixed-corotated stress (polar decomposition and its hand-written
+    gradient) over whole trajectories: state, E and actuation gradients of a
+    random functional against the oracle."""
+    from dataclasses import replace
+    sc = replace(scenes.make(name).with_steps(T), model=1)
+    act = act_table(sc, T)
+    w = random_seed(sc, 10)
+    g = gpu_run(sc, T, act=act, seed=w, knobs=knobs)
+    o = oracle_run(sc, T, act=act, seed=w)
+    compare(f"{name}@{T} corotated {knobs}", sc, g, o, grads=("x", "v", "C", "F"))
+    if act is not None:
+        assert cos(g["gact"], o["gact"]) >= 0.999 and rel(g["gact"], o["gact"]) <= 1e-3
 
