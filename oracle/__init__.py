@@ -9,8 +9,9 @@ robot and its adjoint.
 
 Scenes are described by any object with the attributes ``dim, n_grid, bound,
 dx, dt, gravity, offsets, E, nu, vol, rho, act_id, n_act, act_strength`` and
-optionally ``model`` (0 neo-Hookean, 1 fixed-corotated; duck-typed, so this
-module imports nothing from the GPU package).
+optionally ``model`` (0 neo-Hookean, 1 fixed-corotated) and ``mat_id`` (per
+particle, 1 for the weakly compressible liquid; duck-typed, so this module
+imports nothing from the GPU package).
 
 State layout here: ``x (N, d), v (N, d), C (N, d, d), F (N, d, d)`` float64,
 packed particle-major into one (N, S) array with S = 2d + 2d^2.
@@ -52,6 +53,7 @@ class _Desc(ctypes.Structure):
         ("vol", ctypes.POINTER(ctypes.c_double)), ("rho", ctypes.POINTER(ctypes.c_double)),
         ("act_id", ctypes.POINTER(ctypes.c_int)),
         ("model", ctypes.c_int),
+        ("mat_id", ctypes.POINTER(ctypes.c_int)),
     ]
 
 
@@ -105,6 +107,8 @@ class _Bound:
         act_id = getattr(sc, "act_id", None)
         self.act_id = None if act_id is None else np.ascontiguousarray(act_id, dtype=np.int32)
         self.n_act = int(getattr(sc, "n_act", 0) or 0)
+        mat_id = getattr(sc, "mat_id", None)
+        self.mat_id = None if mat_id is None else np.ascontiguousarray(mat_id, dtype=np.int32)
         self.desc = _Desc(
             dim=self.dim, n_grid=int(sc.n_grid), bound=int(sc.bound), n_scenes=ns, n_act=self.n_act,
             dx=float(sc.dx), dt=float(sc.dt), gravity=float(sc.gravity),
@@ -113,6 +117,7 @@ class _Bound:
             E=_dptr(self.E), nu=_dptr(self.nu), vol=_dptr(self.vol), rho=_dptr(self.rho),
             act_id=None if self.act_id is None else self.act_id.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
             model=int(getattr(sc, "model", 0) or 0),
+            mat_id=None if self.mat_id is None else self.mat_id.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
         )
 
     @property

@@ -17,6 +17,10 @@
 //     the rotation of the polar decomposition F = R S, whose derivative is the
 //     kind of hand-engineered gradient Section 3 and Appendix C describe for
 //     decompositions computed by iteration;
+//   * a weakly compressible liquid for particles with material id 1 (Appendix
+//     E.1 couples such a liquid with the elastic robot in the same grid): Tait
+//     pressure p = E (J^-gamma - 1), gamma = 7, Kirchhoff stress tau = -p J I =
+//     E (J - J^(1 - gamma)) I, the scene's E acting as the bulk modulus;
 //   * the adjoint of each stage written by hand: for a primal f(X) = Y the
 //     adjoint takes (X, Y*) and ACCUMULATES X* = dL/dX (Section 3 and
 //     Appendix B); the grid is recomputed inside the adjoint step instead of
@@ -67,7 +71,10 @@ struct Desc {
   const double* rho;    // [n_scenes] density (particle mass = rho * vol)
   const int* act_id;    // [N] actuator column per particle, -1 = none; may be null
   int model;            // 0: neo-Hookean, 1: fixed-corotated
+  const int* mat_id;    // [N] material per particle (0 solid, 1 liquid); may be null (all solid)
 };
+
+constexpr double kTaitGamma = 7.0;
 
 int pow3(int d) { return d == 2 ? 9 : 27; }
 int state_size(int d) { return 2 * d + 2 * d * d; }
@@ -272,7 +279,12 @@ int p2g_terms(const Desc& s, int sc, const T* Es, const T* act_s, int p, const P
   } else {
     t.lnJ = std::log(t.J);
   }
-  if (s.model == 1 && re(t.J) > 0.0) {
+  if (s.mat_id && s.mat_id[p] == 1) {
+    // liquid: tau = E (J - J^(1 - gamma)) I (no stress when inverted, flagged above)
+    T val = (re(t.J) > 0.0) ? Es[sc] * (t.J - std::pow(t.J, 1.0 - kTaitGamma)) : T(0.0);
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) t.tau[a][b] = (a == b) ? val : T(0.0);
+  } else if (s.model == 1 && re(t.J) > 0.0) {
     // tau = 2 mu (F - R) F^T + lambda (J - 1) J I
     polar_rotation(d, t.F, t.R);
     for (int a = 0; a < d; ++a)
@@ -629,7 +641,16 @@ int step_bwd(const Desc& s, const double* act_s, const double* in, const double*
     double cof[3][3];
     cofactor(d, t.F, cof);
     double eb = 0.0;
-    if (s.model == 1) {
+    if (s.mat_id && s.mat_id[p] == 1) {
+      // liquid: d tau / dJ = E (1 - (1 - gamma) J^-gamma) I, dJ = cof(F) : dF.
+      if (re(t.J) > 0.0) {
+        double E = s.E[sc], J = t.J;
+        double dval = E * (1.0 - (1.0 - kTaitGamma) * std::pow(J, -kTaitGamma));
+        for (int a = 0; a < d; ++a)
+          for (int b = 0; b < d; ++b) H.F(a, b) += dval * tr * cof[a][b];
+        eb += tr * (J - std::pow(J, 1.0 - kTaitGamma));
+      }
+    } else if (s.model == 1) {
       if (re(t.J) > 0.0) corotated_adjoint(d, t, mat, taubar, H, eb);
     } else {
       // tau = mu (F F^T - I) + lambda ln J I
@@ -671,6 +692,7 @@ struct orc_desc {
   const double* rho;
   const int* act_id;
   int model;
+  const int* mat_id;
 };
 
 static Desc to_desc(const orc_desc* o) {
@@ -679,6 +701,7 @@ static Desc to_desc(const orc_desc* o) {
   s.dx = o->dx; s.dt = o->dt; s.gravity = o->gravity; s.act_strength = o->act_strength;
   s.offsets = o->offsets; s.E = o->E; s.nu = o->nu; s.vol = o->vol; s.rho = o->rho; s.act_id = o->act_id;
   s.model = o->model;
+  s.mat_id = o->mat_id;
   return s;
 }
 

@@ -21,6 +21,8 @@ benchmark used a 2D scene with 6.4K particles whose grid is not stated):
        log-uniform in [500, 8000], per-scene E and nu, 256 steps
   robot3d   3D actuated soft robot (body on four legs), 64^3 grid, 30000 particles,
        16 actuators, 512 steps (the crawler of Appendix E.1, synthetic geometry)
+  coupled3d   robot3d beside 13000 particles of weakly compressible liquid, two-way
+       coupled through the grid (the robot-and-liquid setting of Appendix E.1)
   fd8  8 particles with random C and F, for finite-difference checks
 """
 from __future__ import annotations
@@ -63,6 +65,7 @@ class Scene:
     act_b: Optional[np.ndarray] = None    # float32 (n_act,)
     act_omega: float = 0.0
     model: int = 0                        # 0: neo-Hookean, 1: fixed-corotated
+    mat_id: Optional[np.ndarray] = None   # int32 (N,): 0 solid, 1 weakly compressible liquid
     meta: dict = field(default_factory=dict)
 
     @property
@@ -90,7 +93,8 @@ class Scene:
             self, name=f"{self.name}[{len(scenes)}]", offsets=off, E=self.E[scenes].copy(),
             nu=self.nu[scenes].copy(), vol=self.vol[scenes].copy(), rho=self.rho[scenes].copy(),
             x=self.x[idx].copy(), v=self.v[idx].copy(), C=self.C[idx].copy(), F=self.F[idx].copy(),
-            act_id=None if self.act_id is None else self.act_id[idx].copy())
+            act_id=None if self.act_id is None else self.act_id[idx].copy(),
+            mat_id=None if self.mat_id is None else self.mat_id[idx].copy())
 
 
 def _f32(a):
@@ -268,6 +272,30 @@ def robot3d(seed: int = 5, n_particles: int = 30000, steps: int = 512) -> Scene:
     return s
 
 
+def coupled3d(seed: int = 6, n_liquid: int = 13000, steps: int = 512) -> Scene:
+    """The 3D robot (robot3d, 30000 particles, material 0) beside a block of
+    weakly compressible liquid (material 1, n_liquid particles uniform in
+    [0.5, 0.65] x [0.05, 0.05 + h] x [0.3, 0.65], h set so that the liquid has
+    the robot's particle volume), two-way coupled through the shared grid (the
+    robot-and-liquid setting of Appendix E.1, 30K + 13K particles); the scene's
+    E (20) is the liquid's bulk modulus; loss = -(mean final x) of all particles."""
+    rng = np.random.default_rng(seed)
+    r = robot3d(steps=steps)
+    vol = float(r.vol[0])
+    h = n_liquid * vol / (0.15 * 0.35)
+    lo = np.array([0.5, 0.05, 0.3])
+    hi = np.array([0.65, 0.05 + h, 0.65])
+    xl = rng.uniform(lo, hi, size=(n_liquid, 3))
+    x = np.concatenate([r.x.astype(np.float64), xl])
+    N = x.shape[0]
+    s = replace(r, name="coupled3d", offsets=np.array([0, N], np.int32), x=_f32(x),
+                v=_f32(np.zeros((N, 3))), C=_f32(np.zeros((N, 3, 3))), F=_f32(_identity(N, 3)),
+                act_id=np.concatenate([r.act_id, np.full(n_liquid, -1, np.int32)]).astype(np.int32),
+                mat_id=np.concatenate([np.zeros(r.n_particles, np.int32), np.ones(n_liquid, np.int32)]))
+    s.meta = dict(r.meta, liquid_box=(tuple(lo), tuple(hi)))
+    return s
+
+
 def batched2d(seed: int = 4, n_scenes: int = 256, steps: int = 256) -> Scene:
     """n_scenes independent 2D scenes, each on its own 64^2 grid, with particle counts
     N = round(exp U(ln 500, ln 8000)) in rectangle-union shapes (4 particles per cell,
@@ -311,9 +339,10 @@ def batched2d(seed: int = 4, n_scenes: int = 256, steps: int = 256) -> Scene:
         v=_f32(np.zeros((Nt, 2))), C=_f32(np.zeros((Nt, 2, 2))), F=_f32(_identity(Nt, 2)), loss_axis=0)
 
 
-def fd8(dim: int = 2, seed: int = 5, steps: int = 16) -> Scene:
+def fd8(dim: int = 2, seed: int = 5, steps: int = 16, liquid: bool = False) -> Scene:
     """8 particles (2x4 in 2D, 2x2x2 in 3D) near the centre of a 16^d grid, spaced dx/2,
-    with F = I + 0.05 N(0,1), C ~ N(0, 1), v ~ N(0, 0.2): every term of the step is active."""
+    with F = I + 0.05 N(0,1), C ~ N(0, 1), v ~ N(0, 0.2): every term of the step is active.
+    With `liquid`, every other particle is the weakly compressible liquid."""
     rng = np.random.default_rng(seed)
     n = 16
     dx = 1.0 / n
@@ -324,6 +353,8 @@ def fd8(dim: int = 2, seed: int = 5, steps: int = 16) -> Scene:
                 (dx / 2) ** dim)
     s.C = _f32(rng.normal(0.0, 1.0, (8, dim, dim)))
     s.F = _f32(np.eye(dim) + 0.05 * rng.normal(0.0, 1.0, (8, dim, dim)))
+    if liquid:
+        s.mat_id = (np.arange(8) % 2).astype(np.int32)
     return s
 
 
@@ -339,7 +370,7 @@ def random_state(scene: Scene, seed: int, c_scale: float = 1.0, f_scale: float =
 
 
 REGISTRY = {"translate2d": translate2d, "deform2d": deform2d, "actuated2d": actuated2d, "elastic3d": elastic3d, "elastic3d_long": elastic3d_long, "batched2d": batched2d,
-            "robot3d": robot3d}
+            "robot3d": robot3d, "coupled3d": coupled3d}
 
 
 def make(name: str, **kw) -> Scene:

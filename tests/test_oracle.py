@@ -181,6 +181,28 @@ def test_corotated_stress_closed_form(dim):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
+def test_liquid_stress_closed_form(dim):
+    """A liquid particle (material 1) with F = diag(s) and with a sheared F of
+    the same determinant: the stress read back through the grid's second
+    moment is E (J - J^(1 - 7)) I in both cases (pressure only)."""
+    n = 16
+    dx = 1.0 / n
+    x = np.array([7.3, 8.6, 7.9][:dim]) * dx
+    E = 10.0
+    s = np.array([1.04, 0.93, 1.02][:dim])
+    J = np.prod(s)
+    shear = np.eye(dim)
+    shear[0, 1] = 0.3
+    delta = _node_coords(n, dim) * dx - x
+    for F in (np.diag(s), np.diag(s) @ shear):
+        sc = replace(_one_particle(dim, x, F=F, n=n, E=E), mat_id=np.array([1], np.int32))
+        gp, _, err = orc.grid(sc, _state(sc))
+        assert err == 0
+        tau = -(gp[0, :, 1:].T @ delta) / (sc.dt * sc.vol[0])
+        np.testing.assert_allclose(tau, E * (J - J ** (1 - 7)) * np.eye(dim), rtol=1e-11, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
 def test_corotated_frame_indifference(dim):
     """tau(Q F) = Q tau(F) Q^T for the fixed-corotated stress of a generic F."""
     n = 16
@@ -274,15 +296,15 @@ def test_mirror_symmetry(dim, axis):
 # The adjoint: dot-product test against complex-step tangents, finite
 # differences, checkpoint equivalence, batch independence.
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model,liquid", [(0, False), (1, False), (0, True)])
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("T", [1, 12])
-def test_dot_product_complex_step(dim, T, model):
+def test_dot_product_complex_step(dim, T, model, liquid):
     """<J u, w> (complex-step tangent of the forward) equals <u, J^T w> (the
     hand-written reverse pass) for random u (state and E) and w; model 1 runs
     the fixed-corotated stress, whose reverse differentiates the polar
-    decomposition by hand."""
-    sc = replace(scenes.fd8(dim, steps=T), model=model)
+    decomposition by hand; `liquid` makes every other particle liquid."""
+    sc = replace(scenes.fd8(dim, steps=T, liquid=liquid), model=model)
     st = _state(sc)
     rng = np.random.default_rng(7 + dim + T)
     u = rng.normal(size=st.shape)
@@ -308,13 +330,13 @@ def test_dot_product_complex_step(dim, T, model):
         assert abs(l2 - r2) <= 1e-11 * max(abs(l2), 1.0), (blk, l2, r2)
 
 
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model,liquid", [(0, False), (1, False), (0, True)])
 @pytest.mark.parametrize("dim", [2, 3])
-def test_finite_differences_fd8(dim, model):
+def test_finite_differences_fd8(dim, model, liquid):
     """Central differences (h = 1e-6) of a random linear functional of the state
     after 16 steps, with respect to every input component and E, against the
     reverse pass: relative error <= 1e-6."""
-    sc = replace(scenes.fd8(dim, steps=16), model=model)
+    sc = replace(scenes.fd8(dim, steps=16, liquid=liquid), model=model)
     st = _state(sc)
     T = sc.steps
     rng = np.random.default_rng(11)
