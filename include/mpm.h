@@ -116,7 +116,12 @@ typedef struct {
  *   rho      [n_scenes] density; particle mass m_p = rho * vol.
  *   act_id   [N] actuator column of each particle (-1: none) or NULL.
  *   act      [n_steps][n_actuators] actuation values a_k(s) or NULL. For the
- *            single-step calls, row `step` is used. */
+ *            single-step calls, row `step` is used.
+ *   mat_id   [N] material of each particle or NULL (all solid): 0 solid (the
+ *            context's constitutive model), 1 weakly compressible liquid
+ *            (Appendix E.1 couples one with the elastic robot through the
+ *            shared grid): Tait pressure p = E (J^-7 - 1), Kirchhoff stress
+ *            tau = -p J I, the scene's E acting as the bulk modulus. */
 typedef struct {
   const float* E;
   const float* nu;
@@ -124,6 +129,7 @@ typedef struct {
   const float* rho;
   const int32_t* act_id;
   const float* act;
+  const int32_t* mat_id;
 } mpm_params;
 
 /* Gradients with respect to the parameters (device pointers, accumulate).

@@ -48,7 +48,7 @@ class mpm_state(ctypes.Structure):
 
 class mpm_params(ctypes.Structure):
     _fields_ = [("E", c_void_p), ("nu", c_void_p), ("vol", c_void_p), ("rho", c_void_p), ("act_id", c_void_p),
-                ("act", c_void_p)]
+                ("act", c_void_p), ("mat_id", c_void_p)]
 
 
 class mpm_param_grad(ctypes.Structure):

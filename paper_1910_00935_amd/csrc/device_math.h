@@ -229,7 +229,7 @@ __device__ __forceinline__ void polar_rotation(const float (&F)[D][D], float (&R
 }
 
 struct SceneParams {
-  float mass, vol, mu, lam, dmu_dE, dlam_dE;
+  float mass, vol, E, mu, lam, dmu_dE, dlam_dE;
 };
 
 __device__ __forceinline__ SceneParams scene_params(const float* E, const float* nu, const float* vol,
@@ -240,6 +240,7 @@ __device__ __forceinline__ SceneParams scene_params(const float* E, const float*
   p.mass = rho[sc] * p.vol;
   p.dmu_dE = 1.0f / (2.0f * (1.0f + n));
   p.dlam_dE = n / ((1.0f + n) * (1.0f - 2.0f * n));
+  p.E = e;
   p.mu = e * p.dmu_dE;
   p.lam = e * p.dlam_dE;
   return p;
@@ -389,6 +390,48 @@ __device__ __forceinline__ float corotated_adjoint(const PState<D>& p, const Sce
       eb += tb[a][b] * (2.0f * sp.dmu_dE * frf + (a == b ? sp.dlam_dE * (J - 1.0f) * J : 0.0f));
     }
   return eb;
+}
+
+// Weakly compressible liquid (material 1): Tait pressure p = E (J^-7 - 1) with
+// the scene's E as bulk modulus, Kirchhoff stress tau = -p J I = E (J - J^-6) I;
+// an inverted F raises the error bit and carries no stress.
+template <int D>
+__device__ __forceinline__ void affine_liquid(const PState<D>& p, const SceneParams& sp, float act_tau, float dt,
+                                              float kappa, float (&A)[D][D], float& J, unsigned& err) {
+  J = det<D>(p.F);
+  const bool ok = J > 0.0f;
+  if (!ok) err |= kErrInverted;
+  const float ji = 1.0f / J, ji2 = ji * ji;
+  const float val = ok ? sp.E * (J - ji2 * ji2 * ji2) : 0.0f;
+  const float k = dt * sp.vol * kappa;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float tau = (a == b) ? val : 0.0f;
+      if (a == 1 && b == 1) tau += act_tau;
+      A[a][b] = sp.mass * p.C[a][b] - k * tau;
+    }
+}
+
+// Adjoint of the liquid stress: d tau / dJ = E (1 + 6 J^-7) I and dJ =
+// cof(F) : dF, so F* += E (1 + 6 J^-7) tr(tb) cof(F); returns dL/dE.
+template <int D>
+__device__ __forceinline__ float liquid_adjoint(const PState<D>& p, const SceneParams& sp, float J,
+                                                const float (&tb)[D][D], float (&gF)[D][D]) {
+  if (!(J > 0.0f)) return 0.0f;
+  float K[D][D];
+  cofactor<D>(p.F, K);
+  float tr = 0.0f;
+#pragma unroll
+  for (int a = 0; a < D; ++a) tr += tb[a][a];
+  const float ji = 1.0f / J, ji2 = ji * ji, ji6 = ji2 * ji2 * ji2;
+  const float c = sp.E * (1.0f + 6.0f * ji6 * ji) * tr;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) gF[a][b] += c * K[a][b];
+  return tr * (J - ji6);
 }
 
 __device__ __forceinline__ bool interior1(int i, int n, int bound) { return i >= bound && i < n - bound; }

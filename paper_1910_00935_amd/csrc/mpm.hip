@@ -42,6 +42,7 @@ enum Region {
   R_BSUMS,     // scan block sums
   R_SCENE_ID,  // N int32
   R_ACT_ID,    // N int32, sorted actuator ids
+  R_MAT_ID,    // N int32, sorted material ids
   R_OFFSETS,   // n_scenes + 1 int32
   R_GE,        // n_scenes double
   R_GACT,      // kMaxAct double (single-step adjoint)
@@ -175,7 +176,10 @@ StateRef user_ref(const mpm_ctx& c, const mpm_state* s) {
   return StateRef{s->x, s->v, s->C, s->F, c.N};
 }
 
-StepConsts consts(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
+// `sorted`: the launch runs on the tape's sorted particle order (per-particle
+// ids gathered into R_ACT_ID, R_MAT_ID) rather than the caller's.
+StepConsts consts(const mpm_ctx& c, const mpm_params* p, bool sorted) {
+  const int* act_id = p->act_id ? (sorted ? c.at<int>(R_ACT_ID) : p->act_id) : nullptr;
   StepConsts k;
   k.N = c.N;
   k.n = c.n;
@@ -199,6 +203,7 @@ StepConsts consts(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
   k.vol = p->vol;
   k.rho = p->rho;
   k.act_id = (c.n_act > 0) ? act_id : nullptr;
+  k.mat_id = p->mat_id ? (sorted ? c.at<int>(R_MAT_ID) : p->mat_id) : nullptr;
   k.err = c.at<unsigned>(R_ERR);
   return k;
 }
@@ -378,17 +383,17 @@ mpm_status bwd(const mpm_ctx& c, const BwdArgs& a, hipStream_t st) {
   return c.lanes == 2 ? launch_bwd<3, 2>(c, a, st) : launch_bwd<3, 1>(c, a, st);
 }
 
-FwdArgs fwd_args(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
+FwdArgs fwd_args(const mpm_ctx& c, const mpm_params* p, bool sorted) {
   FwdArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.k = consts(c, p, act_id);
+  a.k = consts(c, p, sorted);
   return a;
 }
 
-BwdArgs bwd_args(const mpm_ctx& c, const mpm_params* p, const int* act_id) {
+BwdArgs bwd_args(const mpm_ctx& c, const mpm_params* p, bool sorted) {
   BwdArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.k = consts(c, p, act_id);
+  a.k = consts(c, p, sorted);
   a.partial = c.at<float>(R_PARTIAL);
   a.pstride = c.Np;
   return a;
@@ -493,9 +498,8 @@ mpm_status scatter_state(const mpm_ctx& c, StateRef src, StateRef dst, const int
 // states t0+1 .. t1 into their slots, using the three forward grids.
 mpm_status run_forward(mpm_tape& tp, const mpm_params* p, int t0, int t1, hipStream_t s) {
   const mpm_ctx& c = *tp.ctx;
-  const int* act_id = p->act_id ? c.at<int>(R_ACT_ID) : nullptr;
   for (int k = 0; k < 3; ++k) TRY(zero_grid(c, kGridF + k, s));
-  FwdArgs a = fwd_args(c, p, act_id);
+  FwdArgs a = fwd_args(c, p, true);
   a.in = tp.slot(t0);
   a.grid_out = c.grid(kGridF);
   a.box_out = scatter_into(c, kGridF);
@@ -504,7 +508,7 @@ mpm_status run_forward(mpm_tape& tp, const mpm_params* p, int t0, int t1, hipStr
   TRY(fwd(c, a, s));
   for (int t = t0; t < t1; ++t) {
     const int u = t - t0;
-    FwdArgs b = fwd_args(c, p, act_id);
+    FwdArgs b = fwd_args(c, p, true);
     b.in = tp.slot(t);
     b.out = tp.slot(t + 1);
     b.grid_in = c.grid(kGridF + u % 3);
@@ -564,7 +568,7 @@ mpm_status update_blocks(mpm_ctx& c) {
 }
 
 bool same_params(const mpm_params& a, const mpm_params* b) {
-  return a.E == b->E && a.nu == b->nu && a.vol == b->vol && a.rho == b->rho && a.act_id == b->act_id &&
+  return a.E == b->E && a.nu == b->nu && a.vol == b->vol && a.rho == b->rho && a.act_id == b->act_id && a.mat_id == b->mat_id &&
          a.act == b->act;
 }
 
@@ -644,6 +648,7 @@ mpm_status mpm_init(const mpm_desc* desc, mpm_ctx** out) {
   c->bytes[R_BSUMS] = size_t((c->n_keys + mpm::kScanChunk - 1) / mpm::kScanChunk + 1) * sizeof(int);
   c->bytes[R_SCENE_ID] = N * sizeof(int);
   c->bytes[R_ACT_ID] = N * sizeof(int);
+  c->bytes[R_MAT_ID] = N * sizeof(int);
   c->bytes[R_OFFSETS] = size_t(c->ns + 1) * sizeof(int);
   c->bytes[R_GE] = size_t(c->ns) * sizeof(double);
   c->bytes[R_GACT] = size_t(mpm::kMaxAct) * sizeof(double);
@@ -775,13 +780,13 @@ mpm_status mpm_step_fwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, co
   float4* g = c.grid(kGridB);
   TRY(zero_f4(c, g, c.grid_f4(), s));
   c.gstate[kGridB] = kDirty;  // written below without a box record
-  FwdArgs a = fwd_args(c, params, params->act_id);
+  FwdArgs a = fwd_args(c, params, false);
   a.in = user_ref(c, in);
   a.grid_out = g;
   a.act_row = act_row(c, params, step);
   a.do_p2g = 1;
   TRY(fwd(c, a, s));
-  FwdArgs b = fwd_args(c, params, params->act_id);
+  FwdArgs b = fwd_args(c, params, false);
   b.in = user_ref(c, in);
   b.out = user_ref(c, out);
   b.grid_in = g;
@@ -805,14 +810,14 @@ mpm_status mpm_step_bwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, co
   c.gstate[kGridB] = c.gstate[kAdj] = kDirty;  // written below without a box record
   TRY(zero_f64(c.at<double>(R_GE), c.ns, s));
   TRY(zero_f64(c.at<double>(R_GACT), mpm::kMaxAct, s));
-  FwdArgs a = fwd_args(c, params, params->act_id);
+  FwdArgs a = fwd_args(c, params, false);
   a.in = user_ref(c, in);
   a.grid_out = g;
   a.act_row = act_row(c, params, step);
   a.do_p2g = 1;
   TRY(fwd(c, a, s));
   // Seed -> g2p*(step): scatter into the adjoint grid, keep x*, F* partials.
-  BwdArgs b = bwd_args(c, params, params->act_id);
+  BwdArgs b = bwd_args(c, params, false);
   b.a_mode = 0;
   b.seed = user_ref(c, out_grad);
   b.stB = user_ref(c, in);
@@ -821,7 +826,7 @@ mpm_status mpm_step_bwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, co
   b.aB = ad;
   TRY(bwd(c, b, s));
   // p2g*(step) and output.
-  BwdArgs e = bwd_args(c, params, params->act_id);
+  BwdArgs e = bwd_args(c, params, false);
   e.a_mode = 1;
   e.stA = user_ref(c, in);
   e.gA = g;
@@ -908,6 +913,12 @@ mpm_status enqueue_tape_forward(mpm_tape* tape, const mpm_params* params, const 
                        c.at<int>(R_ACT_ID), perm, c.N);
     LAUNCH_TRY();
   }
+  if (params->mat_id) {
+    span_close(c);
+    hipLaunchKernelGGL(mpm::k_gather_i32, dim3((c.N + 255) / 256), dim3(256), 0, s, params->mat_id,
+                       c.at<int>(R_MAT_ID), perm, c.N);
+    LAUNCH_TRY();
+  }
   TRY(run_forward(*tape, params, 0, tape->T, s));
   TRY(scatter_state(c, tape->slot(tape->T), user_ref(c, final_state), perm, s));
   return MPM_OK;
@@ -918,7 +929,6 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
   mpm_ctx& c = *tape->ctx;
   const int T = tape->T;
   const int* perm = c.at<int>(R_PERM);
-  const int* act_id = params->act_id ? c.at<int>(R_ACT_ID) : nullptr;
   const size_t Np = size_t(c.Np);
   float* seedb = c.at<float>(R_SEED);
   const StateRef seed{seedb, seedb + c.d * Np, seedb + 2 * c.d * Np, seedb + (2 * c.d + c.d * c.d) * Np, c.Np};
@@ -934,7 +944,7 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
 
   TRY(ensure_state(*tape, params, T - 1, s));
   {
-    FwdArgs a = fwd_args(c, params, act_id);
+    FwdArgs a = fwd_args(c, params, true);
     a.in = tape->slot(T - 1);
     a.grid_out = gB(T - 1);
     a.box_out = scatter_into(c, iB(T - 1));
@@ -946,7 +956,7 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
     TRY(ensure_state(*tape, params, st, s));
     if (st >= 1) TRY(ensure_state(*tape, params, st - 1, s));
     if (st + 1 < T) TRY(ensure_state(*tape, params, st + 1, s));
-    BwdArgs b = bwd_args(c, params, act_id);
+    BwdArgs b = bwd_args(c, params, true);
     if (st == T - 1) {
       b.a_mode = 0;
       b.seed = seed;
@@ -983,7 +993,7 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
     TRY(bwd(c, b, s));
   }
   {
-    BwdArgs b = bwd_args(c, params, act_id);
+    BwdArgs b = bwd_args(c, params, true);
     b.a_mode = 1;
     b.stA = tape->slot(0);
     b.gA = gB(0);
@@ -1027,6 +1037,7 @@ std::vector<uintptr_t> graph_key(const mpm_tape* tape, int kind, const mpm_param
                               reinterpret_cast<uintptr_t>(p->E), reinterpret_cast<uintptr_t>(p->nu),
                               reinterpret_cast<uintptr_t>(p->vol), reinterpret_cast<uintptr_t>(p->rho),
                               reinterpret_cast<uintptr_t>(p->act_id), reinterpret_cast<uintptr_t>(p->act),
+                              reinterpret_cast<uintptr_t>(p->mat_id),
                               reinterpret_cast<uintptr_t>(pg ? pg->E : nullptr),
                               reinterpret_cast<uintptr_t>(pg ? pg->act : nullptr)};
   push_state_key(k, a);

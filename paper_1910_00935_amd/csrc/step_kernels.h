@@ -60,6 +60,7 @@ struct StepConsts {
   int remap;      // 1: interleave the workgroup's particles across waves (lane_particle)
   int rotate;     // 1: per-lane stencil visiting order (Sten, lane_color)
   float dx, inv_dx, dt, gdt, kappa, act_strength;
+  const int* mat_id;    // [N] material per particle (0 solid, 1 liquid) or null
   const int4* blocks;   // [n_blocks] scene-aligned workgroups (first, count, scene); required with
                         // several scenes, null with one
   int n_blocks;         // workgroups per particle pass
@@ -1209,7 +1210,10 @@ __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i,
     const SceneParams sp = scene_params(k.E, k.nu, k.vol, k.rho, sc);
     float act_tau;
     actuator_of<D>(k, act_row, i, act_tau);
-    if constexpr (M == 1) {
+    if (k.mat_id && k.mat_id[i] == 1) {
+      float J;
+      affine_liquid<D>(p, sp, act_tau, k.dt, k.kappa, A, J, err);
+    } else if constexpr (M == 1) {
       float R[D][D], J;
       affine_corotated<D>(p, sp, act_tau, k.dt, k.kappa, A, R, J, err);
     } else {
@@ -1481,7 +1485,10 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
       aid = actuator_of<D>(k, a.act_rowA, i, act_tau);
       float A[D][D], FFtI[D][D], lnJ, J, R[D][D];
       unsigned dummy = 0;
-      if constexpr (M == 1)
+      const bool liquid = k.mat_id && k.mat_id[i] == 1;
+      if (liquid)
+        affine_liquid<D>(p, sp, act_tau, k.dt, k.kappa, A, J, dummy);
+      else if constexpr (M == 1)
         affine_corotated<D>(p, sp, act_tau, k.dt, k.kappa, A, R, J, dummy);
       else
         affine<D>(p, sp, act_tau, k.dt, k.kappa, A, FFtI, lnJ, J, dummy);
@@ -1506,7 +1513,9 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
         }
         tr += tb[c][c];
       }
-      if constexpr (M == 1) {
+      if (liquid) {
+        eb = liquid_adjoint<D>(p, sp, J, tb, gF);
+      } else if constexpr (M == 1) {
         eb = corotated_adjoint<D>(p, sp, R, J, tb, gF);
       } else {
         // tau = mu (F F^T - I) + lambda ln J I:

@@ -85,10 +85,11 @@ class Params:
     rho: torch.Tensor
     act_id: Optional[torch.Tensor] = None
     act: Optional[torch.Tensor] = None
+    mat_id: Optional[torch.Tensor] = None
 
     def c(self) -> L.mpm_params:
         return L.mpm_params(_ptr(self.E), _ptr(self.nu), _ptr(self.vol), _ptr(self.rho), _ptr(self.act_id),
-                            _ptr(self.act))
+                            _ptr(self.act), _ptr(self.mat_id))
 
 
 # The library's knob defaults (mpm_set_knob in mpm.h), for comparing launch
@@ -203,7 +204,10 @@ def params_for_scene(scene, device="cuda", act: Optional[torch.Tensor] = None) -
     act_id = None
     if scene.act_id is not None:
         act_id = torch.as_tensor(np.asarray(scene.act_id, np.int32), device=device)
-    return Params(f(scene.E), f(scene.nu), f(scene.vol), f(scene.rho), act_id, act)
+    mat_id = None
+    if getattr(scene, "mat_id", None) is not None:
+        mat_id = torch.as_tensor(np.asarray(scene.mat_id, np.int32), device=device)
+    return Params(f(scene.E), f(scene.nu), f(scene.vol), f(scene.rho), act_id, act, mat_id)
 
 
 def state_for_scene(scene, device="cuda") -> State:

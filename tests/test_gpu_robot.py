@@ -11,7 +11,7 @@ from paper_1910_00935_amd import runtime as rt
 from paper_1910_00935_amd import scenes
 from paper_1910_00935_amd.controller import OpenLoopController
 
-from parity import G_COS, G_REL, act_table, compare, cos, gpu_run, log, oracle_run, rel
+from parity import G_COS, G_REL, act_table, compare, cos, gpu_run, log, oracle_run, random_seed, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -66,3 +66,20 @@ def test_robot3d_autograd_gradient_and_optimisation():
     hist = ctl.optimize(iters=4, lr=0.05)
     log(f"  losses {['%.6f' % v for v in hist]}")
     assert hist[1] < hist[0] and hist[-1] < hist[0]
+
+
+@pytest.mark.parametrize("part", [1, 0])
+def test_coupled_robot_and_liquid(part):
+    """The robot beside 13000 liquid particles (43000 in all), two-way coupled
+    through the grid, over 48 steps: trajectory, state, E and actuation
+    gradients of a random functional against the oracle."""
+    T = 48
+    sc = scenes.coupled3d().with_steps(T)
+    act = act_table(sc, T)
+    w = random_seed(sc, 12)
+    g = gpu_run(sc, T, act=act, seed=w, knobs={"block": 128, "part": part})
+    o = oracle_run(sc, T, act=act, seed=w)
+    log(f"  oracle {o['seconds']:.1f} s")
+    compare(f"coupled3d@{T} part={part}", sc, g, o, grads=("x", "v", "C", "F"))
+    assert cos(g["gact"], o["gact"]) >= G_COS and rel(g["gact"], o["gact"]) <= G_REL
+

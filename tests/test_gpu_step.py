@@ -15,7 +15,7 @@ from parity import cos, log, rel
 pytestmark = pytest.mark.gpu
 
 
-def _case(dim, n_keep, model=0):
+def _case(dim, n_keep, model=0, liquid=False):
     base = scenes.deform2d() if dim == 2 else scenes.elastic3d()
     if n_keep < base.n_particles:
         idx = np.sort(np.random.default_rng(1).choice(base.n_particles, n_keep, replace=False))
@@ -24,15 +24,18 @@ def _case(dim, n_keep, model=0):
         base = replace(base, offsets=np.array([0, n_keep], np.int32), x=base.x[idx], v=base.v[idx],
                        C=base.C[idx], F=base.F[idx])
     from dataclasses import replace as _replace
-    return _replace(scenes.random_state(base, seed=10 + dim), model=model)
+    sc = _replace(scenes.random_state(base, seed=10 + dim), model=model)
+    if liquid:  # every other particle is the weakly compressible liquid
+        sc = _replace(sc, mat_id=(np.arange(sc.n_particles) % 2).astype(np.int32))
+    return sc
 
 
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model,liquid", [(0, False), (1, False), (0, True)])
 @pytest.mark.parametrize("lanes", [1, 2, 4])
 @pytest.mark.parametrize("dim,n_keep", [(2, 1024), (2, 777), (3, 4099)])
-def test_step_fwd_matches_oracle(dim, n_keep, lanes, model):
-    sc = _case(dim, n_keep, model)
-    log(f"[step_fwd] dim={dim} N={sc.n_particles} lanes={lanes} model={model}")
+def test_step_fwd_matches_oracle(dim, n_keep, lanes, model, liquid):
+    sc = _case(dim, n_keep, model, liquid)
+    log(f"[step_fwd] dim={dim} N={sc.n_particles} lanes={lanes} model={model} liquid={liquid}")
     sim = rt.Simulator.for_scene(sc, knobs={"lanes": lanes})
     p = rt.params_for_scene(sc)
     s_in = rt.state_for_scene(sc)
@@ -50,12 +53,12 @@ def test_step_fwd_matches_oracle(dim, n_keep, lanes, model):
     assert r[0] < 2e-7 and max(r[1:]) < 2e-5, r
 
 
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model,liquid", [(0, False), (1, False), (0, True)])
 @pytest.mark.parametrize("lanes", [1, 2, 4])
 @pytest.mark.parametrize("dim,n_keep", [(2, 1024), (2, 777), (3, 4099)])
-def test_step_bwd_matches_oracle(dim, n_keep, lanes, model):
-    sc = _case(dim, n_keep, model)
-    log(f"[step_bwd] dim={dim} N={sc.n_particles} lanes={lanes} model={model}")
+def test_step_bwd_matches_oracle(dim, n_keep, lanes, model, liquid):
+    sc = _case(dim, n_keep, model, liquid)
+    log(f"[step_bwd] dim={dim} N={sc.n_particles} lanes={lanes} model={model} liquid={liquid}")
     S = 2 * dim + 2 * dim * dim
     gout = np.random.default_rng(3).normal(size=(sc.n_particles, S))
     gx, gv, gC, gF = orc.unpack(gout, dim)
