@@ -344,12 +344,13 @@ def run_corotated(args, torch, rt, scenes, knobs):
             "particle_steps_per_s": N * T * args.steps / secs, "ms_per_trajectory": secs * 1e3 / args.steps}
 
 
-def run_robot3d(args, torch, rt, scenes, iters=3):
-    """The 3D actuated robot (16 actuators, 30000 particles, 512 steps): open-loop
-    controller optimisation iterations (actuation signal, tape forward, loss,
-    reverse replay, actuation adjoint, weight update), timed after one warmup."""
+def run_robot3d(args, torch, rt, scenes, iters=3, name="robot3d"):
+    """The 3D actuated robot (16 actuators, 30000 particles, 512 steps; with
+    name="coupled3d", beside 13000 liquid particles): open-loop controller
+    optimisation iterations (actuation signal, tape forward, loss, reverse
+    replay, actuation adjoint, weight update), timed after one warmup."""
     from paper_1910_00935_amd.controller import OpenLoopController
-    sc = scenes.robot3d()
+    sc = scenes.make(name)
     knobs = tuned_knobs(sc, args)
     ctl = OpenLoopController(sc, knobs=knobs)
     hist = [ctl.step(0.05)]
@@ -361,7 +362,8 @@ def run_robot3d(args, torch, rt, scenes, iters=3):
     secs = time.perf_counter() - t0
     if ctl.sim.check_errors():
         raise RuntimeError("robot3d: simulation error flags set")
-    return {"workload": f"3D actuated robot, 64^3 grid, {sc.n_particles} particles, {sc.n_act} actuators, "
+    what = "3D actuated robot" if name == "robot3d" else "3D actuated robot beside weakly compressible liquid"
+    return {"workload": f"{what}, 64^3 grid, {sc.n_particles} particles, {sc.n_act} actuators, "
                         f"{sc.steps} steps; one optimisation iteration = fwd + loss + bwd + weight update",
             "particle_steps_per_s": sc.n_particles * sc.steps * iters / secs,
             "ms_per_iteration": secs * 1e3 / iters, "losses": [round(v, 6) for v in hist], "knobs": knobs}
@@ -448,6 +450,8 @@ def main():
     if not args.no_robot:
         print("[bench] 3D robot controller optimisation", flush=True)
         out["robot3d"] = run_robot3d(args, torch, rt, scenes)
+        print("[bench] 3D robot and liquid controller optimisation", flush=True)
+        out["coupled3d"] = run_robot3d(args, torch, rt, scenes, name="coupled3d")
         print("[bench] fixed-corotated model", flush=True)
         out["elastic3d_corotated"] = run_corotated(args, torch, rt, scenes, elastic3d["knobs"])
     if not args.no_cpu_baseline:
