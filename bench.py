@@ -138,6 +138,8 @@ def run_elastic3d(args, torch, rt, scenes):
         "bytes_per_launch": dom["bytes"], "mean_launch_us": round(dom["ms"] * 1e3, 3),
         "kernels": {k: {"mean_launch_us": round(v["ms"] * 1e3, 3), "launches": v["launches"],
                         "alg_bytes_per_launch": v["bytes"]} for k, v in per.items()},
+        # Context for frac: a streaming launch of the same byte count, no dependent work.
+        "copy_same_bytes": copy_ceiling(torch, dom["bytes"]),
     }
     return {
         "value": value, "ms_per_step": secs * 1e3 / args.steps, "N": N, "T": T, "roofline": roofline, "knobs": knobs,
@@ -147,6 +149,30 @@ def run_elastic3d(args, torch, rt, scenes):
 
 
 COPY_MIB = 64  # calibration copy: reads and writes exactly this many MiB
+
+
+def copy_ceiling(torch, nbytes, launches=200):
+    """Mean duration of a plain streaming kernel that reads nbytes/2 and writes
+    nbytes/2 (an elementwise scale, back to back on one stream): the HBM
+    fraction a launch moving this many bytes reaches with no dependent work."""
+    n = max(nbytes // 8, 1)
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(10):
+        torch.mul(src, 1.0, out=dst)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(launches):
+        torch.mul(src, 1.0, out=dst)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / launches
+    gbs = 8 * n / (us * 1e-6) / 1e9
+    return {"bytes": 8 * n, "mean_launch_us": round(us, 3), "achieved": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def calibration_copy(torch):
