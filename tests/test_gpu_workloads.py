@@ -130,6 +130,8 @@ def test_error_flags():
     F = base.F.copy()
     F[7] = np.diag([-1.0, 1.0])
     cases.append(("inverted", replace(base, F=F), 2))
+    cases.append(("inverted corotated", replace(base, F=F, model=1), 2))
+    cases.append(("inverted liquid", replace(base, F=F, mat_id=(np.arange(base.n_particles) % 2).astype(np.int32)), 2))
     v = base.v.copy()
     v[9, 0] = np.nan
     cases.append(("nonfinite", replace(base, v=v), 4))
