@@ -58,12 +58,22 @@ class _Desc(ctypes.Structure):
 
 
 _lib = None
+_override = None
+
+
+def use_library(path=None):
+    """Point this module at another build of the oracle (a copy with a planted
+    mistake, for the tests that check that the pins catch it); None restores
+    the library built from ``mpm_oracle.cpp``."""
+    global _lib, _override
+    _override = path
+    _lib = None
 
 
 def _load():
     global _lib
     if _lib is None:
-        lib = ctypes.CDLL(build())
+        lib = ctypes.CDLL(_override or build())
         D = ctypes.POINTER(_Desc)
         P = ctypes.POINTER(ctypes.c_double)
         i = ctypes.c_int
