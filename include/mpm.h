@@ -229,17 +229,33 @@ void mpm_tape_destroy(mpm_tape* tape);
 
 /* Runs n_steps forward steps from `init` (caller order) and writes the final
  * state to `final` (caller order). Internally particles are sorted by scene
- * and cell (Morton order) once, at step 0, and the tape keeps sorted states.
- * Records the parameter pointers for the reverse pass. */
+ * and cell (Morton order, as mpm_sort_order) once, at step 0, and the tape
+ * keeps sorted states together with the permutation, the sorted actuator and
+ * material ids and the workgroup table of that order. Records the parameter
+ * pointers and the launch shape (knobs "block", "lanes", "part") for the
+ * reverse pass. A second forward on the same tape replaces the recorded
+ * trajectory. */
 mpm_status mpm_tape_forward(mpm_tape* tape, const mpm_params* params, const mpm_state* init, mpm_state* final_state,
                             void* stream);
 
 /* Reverse pass over the recorded trajectory: given final_grad = dL/d(final
  * state) (caller order), ADDS dL/d(init) into init_grad (caller order) and
- * dL/dE, dL/da into pg. MPM_E_TAPE if no forward was recorded or if params
- * differ from the recorded ones. May be called repeatedly after one forward. */
+ * dL/dE, dL/da into pg. MPM_E_TAPE if no forward was recorded, if params
+ * differ from the recorded ones, or if the launch shape changed since the
+ * forward. May be called repeatedly after one forward; other tapes of the
+ * same context may run in between. */
 mpm_status mpm_tape_backward(mpm_tape* tape, const mpm_params* params, const mpm_state* final_grad,
                              mpm_state* init_grad, mpm_param_grad* pg, void* stream);
+
+/* Binning (support call; the paper's Taichi layouts leave the particle order
+ * to the compiler): the order in which the tape keeps particles. Sorts the
+ * particles of `state` by (scene, cell), cells ordered along the Morton curve
+ * of the scene's grid (cell c_a = floor(x_a / dx) clamped into [0, n_grid - 1],
+ * NaN to 0; axis 0 the most significant bit of each level), keeping the
+ * caller's order among particles of one cell, and writes perm[j] = caller
+ * index of the j-th particle in that order (device int32[N], overwritten).
+ * Asynchronous on `stream`. */
+mpm_status mpm_sort_order(mpm_ctx* ctx, const mpm_state* state, int32_t* perm, void* stream);
 
 /* Loss on a final state (the pattern of the paper's compute_loss kernel):
  * kind MPM_LOSS_MEAN_POS gives, per scene k, L_k = sign * mean_p x_{p,axis}.

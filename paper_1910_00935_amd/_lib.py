@@ -84,6 +84,7 @@ _SIGNATURES = {
                                    ctypes.POINTER(mpm_state), c_void_p]),
     "mpm_tape_backward": (c_int32, [c_void_p, ctypes.POINTER(mpm_params), ctypes.POINTER(mpm_state),
                                     ctypes.POINTER(mpm_state), ctypes.POINTER(mpm_param_grad), c_void_p]),
+    "mpm_sort_order": (c_int32, [c_void_p, ctypes.POINTER(mpm_state), c_void_p, c_void_p]),
     "mpm_loss": (c_int32, [c_void_p, c_int32, c_int32, c_float, ctypes.POINTER(mpm_state), c_void_p,
                            ctypes.POINTER(mpm_state), c_void_p]),
     "mpm_actuation": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_float, c_int32, c_void_p, c_void_p]),
@@ -186,6 +187,10 @@ def mpm_tape_forward(tape, params, init, final, stream):
 def mpm_tape_backward(tape, params, final_grad, init_grad, pg, stream):
     call("mpm_tape_backward", tape, ctypes.byref(params), ctypes.byref(final_grad), ctypes.byref(init_grad),
          ctypes.byref(pg), c_void_p(stream))
+
+
+def mpm_sort_order(ctx, state, perm, stream):
+    call("mpm_sort_order", ctx, ctypes.byref(state), c_void_p(perm), c_void_p(stream))
 
 
 def mpm_loss(ctx, kind, axis, sign, final, loss_ptr, seed, stream):

@@ -39,8 +39,8 @@ class OpenLoopController:
         """Differentiable loss of one trajectory under the current weights."""
         sc, p = self.scene, self.params
         act = rt.Actuation.apply(self.sim, self.W, self.b, float(sc.act_omega), self.T)
-        xT, _, _, _ = rt.MPMTrajectory.apply(self.tape, self.init.x, self.init.v, self.init.C, self.init.F,
-                                             p.E, p.nu, p.vol, p.rho, p.act_id, act)
+        xT, _, _, _ = rt.MPMTrajectory.apply(self.tape, p, self.init.x, self.init.v, self.init.C, self.init.F, p.E,
+                                             act)
         return float(sc.loss_sign) * xT[int(sc.loss_axis)].mean()
 
     def step(self, lr: float, normalize: bool = True) -> float:

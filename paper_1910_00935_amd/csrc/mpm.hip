@@ -35,19 +35,19 @@ enum Region {
   R_GRID,      // 10 grids: 0-2 forward, 3-6 reverse primal, 7-9 reverse adjoint
   R_PARTIAL,   // (d + d^2) x Np floats
   R_SEED,      // S x Np floats, sorted dL/dstate(T)
-  R_KEYS,      // N uint32
-  R_PERM,      // N int32: sorted index -> caller index
+  R_KEYS,      // N uint32 sort keys (radix passes ping-pong with R_KEYS2)
+  R_KEYS2,     // N uint32
+  R_VALS,      // N int32 radix-pass values
+  R_RHIST,     // kRadix x radix tiles int32: per-tile digit counts, scanned in place
   R_COUNTS,    // n_keys int32
   R_START,     // n_keys int32
   R_BSUMS,     // scan block sums
   R_SCENE_ID,  // N int32
-  R_ACT_ID,    // N int32, sorted actuator ids
-  R_MAT_ID,    // N int32, sorted material ids
   R_OFFSETS,   // n_scenes + 1 int32
   R_GE,        // n_scenes double
   R_GACT,      // kMaxAct double (single-step adjoint)
   R_ERR,       // 1 uint32
-  R_BLOCKS,    // int4 per workgroup: scene-aligned particle ranges (first, count, scene)
+  R_BLOCKS,    // int4 per workgroup: the plain table padded (single steps, in the caller's order)
   R_PLAIN,     // int4 per workgroup: the plain partition (runs of consecutive particles)
   R_PART,      // int32 per parent block: workgroups it emits, scanned
   R_BOXES,     // per grid, 2 int4 per workgroup: nodes its last scatter touched
@@ -123,10 +123,13 @@ struct mpm_tape {
   int T = 0, K = 0;
   bool full = true;
   int n_ckpt = 0, R = 0, n_slots = 0;
-  size_t slot_floats = 0, off_gact = 0, total = 0;
+  size_t slot_floats = 0, off_gact = 0, off_perm = 0, off_act = 0, off_mat = 0, off_blocks = 0, total = 0;
   char* mem = nullptr;
   bool recorded = false;
   mpm_params rec{};
+  // Launch shape the recorded forward sorted and partitioned for (knobs
+  // "block", "lanes", "part"); the reverse pass needs the same.
+  int rec_block = 0, rec_lanes = 0, rec_part = 0;
   std::vector<int> ring_holds;
   // Captured launch sequences (knob "graph"): key = every pointer and size the
   // sequence depends on plus the checkpoint-ring state it starts from; the
@@ -155,6 +158,14 @@ struct mpm_tape {
     return StateRef{b, b + c.d * Np, b + 2 * c.d * Np, b + (2 * c.d + c.d * c.d) * Np, c.Np};
   }
   double* gact() const { return reinterpret_cast<double*>(mem + off_gact); }
+  // The recorded trajectory's sort (sorted index -> caller index), its
+  // per-particle ids in sorted order, and its workgroup table: kept with the
+  // tape, so other tapes of the context may run between its forward and its
+  // reverse pass.
+  int* perm() const { return reinterpret_cast<int*>(mem + off_perm); }
+  int* act_ids() const { return reinterpret_cast<int*>(mem + off_act); }
+  int* mat_ids() const { return reinterpret_cast<int*>(mem + off_mat); }
+  int4* blocks() const { return reinterpret_cast<int4*>(mem + off_blocks); }
 };
 
 namespace {
@@ -176,10 +187,10 @@ StateRef user_ref(const mpm_ctx& c, const mpm_state* s) {
   return StateRef{s->x, s->v, s->C, s->F, c.N};
 }
 
-// `sorted`: the launch runs on the tape's sorted particle order (per-particle
-// ids gathered into R_ACT_ID, R_MAT_ID) rather than the caller's.
-StepConsts consts(const mpm_ctx& c, const mpm_params* p, bool sorted) {
-  const int* act_id = p->act_id ? (sorted ? c.at<int>(R_ACT_ID) : p->act_id) : nullptr;
+// `tp` non-null: the launch runs on that tape's sorted particle order (its
+// per-particle ids and workgroup table) rather than the caller's.
+StepConsts consts(const mpm_ctx& c, const mpm_params* p, const mpm_tape* tp) {
+  const int* act_id = p->act_id ? (tp ? tp->act_ids() : p->act_id) : nullptr;
   StepConsts k;
   k.N = c.N;
   k.n = c.n;
@@ -196,14 +207,14 @@ StepConsts consts(const mpm_ctx& c, const mpm_params* p, bool sorted) {
   k.lds = c.lds;
   k.remap = c.remap;
   k.rotate = c.rotate;
-  k.blocks = (c.ns > 1 || c.part) ? c.at<int4>(R_BLOCKS) : nullptr;
+  k.blocks = (c.ns > 1 || c.part) ? (tp ? tp->blocks() : c.at<int4>(R_BLOCKS)) : nullptr;
   k.n_blocks = c.n_blocks;
   k.E = p->E;
   k.nu = p->nu;
   k.vol = p->vol;
   k.rho = p->rho;
   k.act_id = (c.n_act > 0) ? act_id : nullptr;
-  k.mat_id = p->mat_id ? (sorted ? c.at<int>(R_MAT_ID) : p->mat_id) : nullptr;
+  k.mat_id = p->mat_id ? (tp ? tp->mat_ids() : p->mat_id) : nullptr;
   k.err = c.at<unsigned>(R_ERR);
   return k;
 }
@@ -383,17 +394,17 @@ mpm_status bwd(const mpm_ctx& c, const BwdArgs& a, hipStream_t st) {
   return c.lanes == 2 ? launch_bwd<3, 2>(c, a, st) : launch_bwd<3, 1>(c, a, st);
 }
 
-FwdArgs fwd_args(const mpm_ctx& c, const mpm_params* p, bool sorted) {
+FwdArgs fwd_args(const mpm_ctx& c, const mpm_params* p, const mpm_tape* tp) {
   FwdArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.k = consts(c, p, sorted);
+  a.k = consts(c, p, tp);
   return a;
 }
 
-BwdArgs bwd_args(const mpm_ctx& c, const mpm_params* p, bool sorted) {
+BwdArgs bwd_args(const mpm_ctx& c, const mpm_params* p, const mpm_tape* tp) {
   BwdArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.k = consts(c, p, sorted);
+  a.k = consts(c, p, tp);
   a.partial = c.at<float>(R_PARTIAL);
   a.pstride = c.Np;
   return a;
@@ -402,7 +413,7 @@ BwdArgs bwd_args(const mpm_ctx& c, const mpm_params* p, bool sorted) {
 // Aligned workgroup table from the cell starts of the last sort (R_START):
 // counts per parent block (into R_COUNTS, free after the sort), their scan,
 // the entries, and the padding (or the plain table if it did not fit).
-mpm_status build_partition(const mpm_ctx& c, hipStream_t s) {
+mpm_status build_partition(const mpm_ctx& c, int4* table, hipStream_t s) {
   const mpm::PartGeom g = part_geom(c, c.block / c.lanes);
   const long n_par = long(g.per_scene) * g.n_scenes;
   int* counts = c.at<int>(R_COUNTS);
@@ -419,17 +430,20 @@ mpm_status build_partition(const mpm_ctx& c, hipStream_t s) {
   hipLaunchKernelGGL(mpm::k_scan_add, dim3(nb), dim3(256), 0, s, offs, n_par, bsums);
   LAUNCH_TRY();
   hipLaunchKernelGGL(mpm::k_part_emit, dim3(pb), dim3(256), 0, s, c.at<int>(R_START), g, counts, offs, c.n_blocks,
-                     c.at<int4>(R_BLOCKS));
+                     table);
   LAUNCH_TRY();
   hipLaunchKernelGGL(mpm::k_part_finish, dim3(1), dim3(256), 0, s, g, counts, offs, c.n_blocks, c.at<int4>(R_PLAIN),
-                     c.n_plain, c.at<int4>(R_BLOCKS));
+                     c.n_plain, table);
   LAUNCH_TRY();
   return MPM_OK;
 }
 
-// Sorts particles by (scene, Morton cell) of `st`; writes R_PERM (and, with
-// `part`, the aligned workgroup table).
-mpm_status sort_particles(const mpm_ctx& c, StateRef st, hipStream_t s) {
+// Sorts particles by (scene, Morton cell) of `st` (a stable radix sort, so
+// particles of one cell keep the caller's order): perm[j] = caller index of
+// the j-th sorted particle. With a table, also writes the workgroup table of
+// the sorted order there (the aligned partition with `part`, else the plain
+// one).
+mpm_status sort_particles(const mpm_ctx& c, StateRef st, int* perm, int4* table, hipStream_t s) {
   span_close(c);
   int* counts = c.at<int>(R_COUNTS);
   int* start = c.at<int>(R_START);
@@ -440,13 +454,15 @@ mpm_status sort_particles(const mpm_ctx& c, StateRef st, hipStream_t s) {
   LAUNCH_TRY();
   const int* sid = c.ns > 1 ? c.at<int>(R_SCENE_ID) : nullptr;
   const int pb = (c.N + 255) / 256;
+  unsigned* keys[2] = {c.at<unsigned>(R_KEYS), c.at<unsigned>(R_KEYS2)};
   if (c.d == 2)
     hipLaunchKernelGGL(mpm::k_sort_keys<2>, dim3(pb), dim3(256), 0, s, st, c.N, sid, 1.0f / c.dx, c.n, c.bits,
-                       c.cells_per_scene, c.at<unsigned>(R_KEYS), counts);
+                       c.cells_per_scene, keys[0], counts);
   else
     hipLaunchKernelGGL(mpm::k_sort_keys<3>, dim3(pb), dim3(256), 0, s, st, c.N, sid, 1.0f / c.dx, c.n, c.bits,
-                       c.cells_per_scene, c.at<unsigned>(R_KEYS), counts);
+                       c.cells_per_scene, keys[0], counts);
   LAUNCH_TRY();
+  // Cell starts (the partition's input).
   const int nb = int((nk + mpm::kScanChunk - 1) / mpm::kScanChunk);
   hipLaunchKernelGGL(mpm::k_scan_blocks, dim3(nb), dim3(mpm::kScanThreads), 0, s, counts, start, nk, bsums);
   LAUNCH_TRY();
@@ -454,15 +470,38 @@ mpm_status sort_particles(const mpm_ctx& c, StateRef st, hipStream_t s) {
   LAUNCH_TRY();
   hipLaunchKernelGGL(mpm::k_scan_add, dim3(nb), dim3(256), 0, s, start, nk, bsums);
   LAUNCH_TRY();
-  hipLaunchKernelGGL(mpm::k_zero_i32, dim3(zb), dim3(256), 0, s, counts, nk);
+  // The permutation: radix passes over the key bits, the last one writing perm.
+  int key_bits = 1;
+  while ((1L << key_bits) < nk) ++key_bits;
+  const int passes = (key_bits + mpm::kRadixBits - 1) / mpm::kRadixBits;
+  const int tiles = (c.N + mpm::kRadixTile - 1) / mpm::kRadixTile;
+  const long hn = long(mpm::kRadix) * tiles;
+  const int hb = int((hn + mpm::kScanChunk - 1) / mpm::kScanChunk);
+  int* hist = c.at<int>(R_RHIST);
+  int* vals[2] = {perm, c.at<int>(R_VALS)};
+  for (int q = 0; q < passes; ++q) {
+    const int shift = q * mpm::kRadixBits;
+    const unsigned* kin = keys[q & 1];
+    unsigned* kout = keys[(q + 1) & 1];
+    const int* vin = q == 0 ? nullptr : vals[(passes - q) & 1];
+    int* vout = vals[(passes - 1 - q) & 1];
+    hipLaunchKernelGGL(mpm::k_radix_hist, dim3(tiles), dim3(mpm::kRadixTile), 0, s, kin, c.N, shift, tiles, hist);
+    LAUNCH_TRY();
+    hipLaunchKernelGGL(mpm::k_scan_blocks, dim3(hb), dim3(mpm::kScanThreads), 0, s, hist, hist, hn, bsums);
+    LAUNCH_TRY();
+    hipLaunchKernelGGL(mpm::k_scan_sums, dim3(1), dim3(mpm::kScanThreads), 0, s, bsums, hb);
+    LAUNCH_TRY();
+    hipLaunchKernelGGL(mpm::k_scan_add, dim3(hb), dim3(256), 0, s, hist, hn, bsums);
+    LAUNCH_TRY();
+    hipLaunchKernelGGL(mpm::k_radix_scatter, dim3(tiles), dim3(mpm::kRadixTile), 0, s, kin, vin, c.N, shift, tiles,
+                       hist, kout, vout);
+    LAUNCH_TRY();
+  }
+  if (!table || !(c.ns > 1 || c.part)) return MPM_OK;
+  if (c.part) return build_partition(c, table, s);
+  hipLaunchKernelGGL(mpm::k_copy_i4, dim3((c.n_blocks + 255) / 256), dim3(256), 0, s, c.at<int4>(R_BLOCKS), table,
+                     c.n_blocks);
   LAUNCH_TRY();
-  hipLaunchKernelGGL(mpm::k_sort_scatter, dim3(pb), dim3(256), 0, s, c.at<unsigned>(R_KEYS), c.N, start, counts,
-                     c.at<int>(R_PERM));
-  LAUNCH_TRY();
-  hipLaunchKernelGGL(mpm::k_sort_fixup, dim3(int((nk + 255) / 256)), dim3(256), 0, s, c.at<int>(R_PERM), start, nk,
-                     c.N);
-  LAUNCH_TRY();
-  if (c.part) return build_partition(c, s);
   return MPM_OK;
 }
 
@@ -499,7 +538,7 @@ mpm_status scatter_state(const mpm_ctx& c, StateRef src, StateRef dst, const int
 mpm_status run_forward(mpm_tape& tp, const mpm_params* p, int t0, int t1, hipStream_t s) {
   const mpm_ctx& c = *tp.ctx;
   for (int k = 0; k < 3; ++k) TRY(zero_grid(c, kGridF + k, s));
-  FwdArgs a = fwd_args(c, p, true);
+  FwdArgs a = fwd_args(c, p, &tp);
   a.in = tp.slot(t0);
   a.grid_out = c.grid(kGridF);
   a.box_out = scatter_into(c, kGridF);
@@ -508,7 +547,7 @@ mpm_status run_forward(mpm_tape& tp, const mpm_params* p, int t0, int t1, hipStr
   TRY(fwd(c, a, s));
   for (int t = t0; t < t1; ++t) {
     const int u = t - t0;
-    FwdArgs b = fwd_args(c, p, true);
+    FwdArgs b = fwd_args(c, p, &tp);
     b.in = tp.slot(t);
     b.out = tp.slot(t + 1);
     b.grid_in = c.grid(kGridF + u % 3);
@@ -642,13 +681,15 @@ mpm_status mpm_init(const mpm_desc* desc, mpm_ctx** out) {
   c->bytes[R_PARTIAL] = size_t(d.dim + d.dim * d.dim) * Np * sizeof(float);
   c->bytes[R_SEED] = size_t(c->S) * Np * sizeof(float);
   c->bytes[R_KEYS] = N * sizeof(unsigned);
-  c->bytes[R_PERM] = N * sizeof(int);
+  c->bytes[R_KEYS2] = N * sizeof(unsigned);
+  c->bytes[R_VALS] = N * sizeof(int);
+  const size_t radix_n = size_t(mpm::kRadix) * ((N + mpm::kRadixTile - 1) / mpm::kRadixTile);
+  c->bytes[R_RHIST] = radix_n * sizeof(int);
   c->bytes[R_COUNTS] = size_t(c->n_keys) * sizeof(int);
   c->bytes[R_START] = size_t(c->n_keys) * sizeof(int);
-  c->bytes[R_BSUMS] = size_t((c->n_keys + mpm::kScanChunk - 1) / mpm::kScanChunk + 1) * sizeof(int);
+  const size_t scan_n = std::max(size_t(c->n_keys), radix_n);
+  c->bytes[R_BSUMS] = size_t((scan_n + mpm::kScanChunk - 1) / mpm::kScanChunk + 1) * sizeof(int);
   c->bytes[R_SCENE_ID] = N * sizeof(int);
-  c->bytes[R_ACT_ID] = N * sizeof(int);
-  c->bytes[R_MAT_ID] = N * sizeof(int);
   c->bytes[R_OFFSETS] = size_t(c->ns + 1) * sizeof(int);
   c->bytes[R_GE] = size_t(c->ns) * sizeof(double);
   c->bytes[R_GACT] = size_t(mpm::kMaxAct) * sizeof(double);
@@ -780,13 +821,13 @@ mpm_status mpm_step_fwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, co
   float4* g = c.grid(kGridB);
   TRY(zero_f4(c, g, c.grid_f4(), s));
   c.gstate[kGridB] = kDirty;  // written below without a box record
-  FwdArgs a = fwd_args(c, params, false);
+  FwdArgs a = fwd_args(c, params, nullptr);
   a.in = user_ref(c, in);
   a.grid_out = g;
   a.act_row = act_row(c, params, step);
   a.do_p2g = 1;
   TRY(fwd(c, a, s));
-  FwdArgs b = fwd_args(c, params, false);
+  FwdArgs b = fwd_args(c, params, nullptr);
   b.in = user_ref(c, in);
   b.out = user_ref(c, out);
   b.grid_in = g;
@@ -810,14 +851,14 @@ mpm_status mpm_step_bwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, co
   c.gstate[kGridB] = c.gstate[kAdj] = kDirty;  // written below without a box record
   TRY(zero_f64(c.at<double>(R_GE), c.ns, s));
   TRY(zero_f64(c.at<double>(R_GACT), mpm::kMaxAct, s));
-  FwdArgs a = fwd_args(c, params, false);
+  FwdArgs a = fwd_args(c, params, nullptr);
   a.in = user_ref(c, in);
   a.grid_out = g;
   a.act_row = act_row(c, params, step);
   a.do_p2g = 1;
   TRY(fwd(c, a, s));
   // Seed -> g2p*(step): scatter into the adjoint grid, keep x*, F* partials.
-  BwdArgs b = bwd_args(c, params, false);
+  BwdArgs b = bwd_args(c, params, nullptr);
   b.a_mode = 0;
   b.seed = user_ref(c, out_grad);
   b.stB = user_ref(c, in);
@@ -826,7 +867,7 @@ mpm_status mpm_step_bwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, co
   b.aB = ad;
   TRY(bwd(c, b, s));
   // p2g*(step) and output.
-  BwdArgs e = bwd_args(c, params, false);
+  BwdArgs e = bwd_args(c, params, nullptr);
   e.a_mode = 1;
   e.stA = user_ref(c, in);
   e.gA = g;
@@ -872,8 +913,13 @@ mpm_status mpm_tape_create(mpm_ctx* ctx, int32_t n_steps, int32_t ckpt_every, mp
   t->n_slots = t->n_ckpt + 1 + t->R;
   t->slot_floats = size_t(ctx->S) * size_t(ctx->Np);
   const size_t slots_bytes = align_up(size_t(t->n_slots) * t->slot_floats * sizeof(float));
+  const size_t N = size_t(ctx->N);
   t->off_gact = slots_bytes;
-  t->total = align_up(slots_bytes + size_t(n_steps) * size_t(std::max(ctx->n_act, 1)) * sizeof(double));
+  t->off_perm = align_up(t->off_gact + size_t(n_steps) * size_t(std::max(ctx->n_act, 1)) * sizeof(double));
+  t->off_act = align_up(t->off_perm + N * sizeof(int));
+  t->off_mat = align_up(t->off_act + N * sizeof(int));
+  t->off_blocks = align_up(t->off_mat + N * sizeof(int));
+  t->total = align_up(t->off_blocks + size_t(ctx->blocks_cap) * sizeof(int4));
   *out = t;
   return MPM_OK;
 }
@@ -904,19 +950,19 @@ mpm_status enqueue_tape_forward(mpm_tape* tape, const mpm_params* params, const 
   mpm_ctx& c = *tape->ctx;
   if (!tape->full) std::fill(tape->ring_holds.begin(), tape->ring_holds.end(), -1);
   const StateRef init_ref = user_ref(c, init);
-  TRY(sort_particles(c, init_ref, s));
-  const int* perm = c.at<int>(R_PERM);
+  TRY(sort_particles(c, init_ref, tape->perm(), tape->blocks(), s));
+  const int* perm = tape->perm();
   TRY(gather_state(c, init_ref, tape->slot(0), perm, s));
   if (params->act_id && c.n_act > 0) {
     span_close(c);
     hipLaunchKernelGGL(mpm::k_gather_i32, dim3((c.N + 255) / 256), dim3(256), 0, s, params->act_id,
-                       c.at<int>(R_ACT_ID), perm, c.N);
+                       tape->act_ids(), perm, c.N);
     LAUNCH_TRY();
   }
   if (params->mat_id) {
     span_close(c);
     hipLaunchKernelGGL(mpm::k_gather_i32, dim3((c.N + 255) / 256), dim3(256), 0, s, params->mat_id,
-                       c.at<int>(R_MAT_ID), perm, c.N);
+                       tape->mat_ids(), perm, c.N);
     LAUNCH_TRY();
   }
   TRY(run_forward(*tape, params, 0, tape->T, s));
@@ -928,7 +974,7 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
                                  mpm_state* init_grad, mpm_param_grad* pg, hipStream_t s) {
   mpm_ctx& c = *tape->ctx;
   const int T = tape->T;
-  const int* perm = c.at<int>(R_PERM);
+  const int* perm = tape->perm();
   const size_t Np = size_t(c.Np);
   float* seedb = c.at<float>(R_SEED);
   const StateRef seed{seedb, seedb + c.d * Np, seedb + 2 * c.d * Np, seedb + (2 * c.d + c.d * c.d) * Np, c.Np};
@@ -944,7 +990,7 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
 
   TRY(ensure_state(*tape, params, T - 1, s));
   {
-    FwdArgs a = fwd_args(c, params, true);
+    FwdArgs a = fwd_args(c, params, tape);
     a.in = tape->slot(T - 1);
     a.grid_out = gB(T - 1);
     a.box_out = scatter_into(c, iB(T - 1));
@@ -956,7 +1002,7 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
     TRY(ensure_state(*tape, params, st, s));
     if (st >= 1) TRY(ensure_state(*tape, params, st - 1, s));
     if (st + 1 < T) TRY(ensure_state(*tape, params, st + 1, s));
-    BwdArgs b = bwd_args(c, params, true);
+    BwdArgs b = bwd_args(c, params, tape);
     if (st == T - 1) {
       b.a_mode = 0;
       b.seed = seed;
@@ -993,7 +1039,7 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
     TRY(bwd(c, b, s));
   }
   {
-    BwdArgs b = bwd_args(c, params, true);
+    BwdArgs b = bwd_args(c, params, tape);
     b.a_mode = 1;
     b.stA = tape->slot(0);
     b.gA = gB(0);
@@ -1100,6 +1146,9 @@ mpm_status mpm_tape_forward(mpm_tape* tape, const mpm_params* params, const mpm_
   TRY(run_graphed(tape, graph_key(tape, 0, params, init, final_state, nullptr), s,
                   [&](hipStream_t cs) { return enqueue_tape_forward(tape, params, init, final_state, cs); }));
   tape->rec = *params;
+  tape->rec_block = tape->ctx->block;
+  tape->rec_lanes = tape->ctx->lanes;
+  tape->rec_part = tape->ctx->part;
   tape->recorded = true;
   return MPM_OK;
 }
@@ -1108,11 +1157,20 @@ mpm_status mpm_tape_backward(mpm_tape* tape, const mpm_params* params, const mpm
                              mpm_state* init_grad, mpm_param_grad* pg, void* stream) {
   if (!tape || !params_ok(params) || !state_ok(final_grad) || !state_ok(init_grad)) return MPM_E_ARG;
   if (!tape->mem || !tape->recorded || !same_params(tape->rec, params)) return MPM_E_TAPE;
+  const mpm_ctx& cx = *tape->ctx;
+  if (cx.block != tape->rec_block || cx.lanes != tape->rec_lanes || cx.part != tape->rec_part) return MPM_E_TAPE;
   if (!tape->ctx->ws) return MPM_E_STATE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const SpanGuard guard(*tape->ctx);
   return run_graphed(tape, graph_key(tape, 1, params, final_grad, init_grad, pg), s,
                      [&](hipStream_t cs) { return enqueue_tape_backward(tape, params, final_grad, init_grad, pg, cs); });
+}
+
+mpm_status mpm_sort_order(mpm_ctx* ctx, const mpm_state* state, int32_t* perm, void* stream) {
+  if (!ctx || !state_ok(state) || !perm) return MPM_E_ARG;
+  if (!ctx->ws) return MPM_E_STATE;
+  const SpanGuard guard(*ctx);
+  return sort_particles(*ctx, user_ref(*ctx, state), perm, nullptr, static_cast<hipStream_t>(stream));
 }
 
 mpm_status mpm_loss(mpm_ctx* ctx, int32_t kind, int32_t axis, float sign, const mpm_state* final_state,

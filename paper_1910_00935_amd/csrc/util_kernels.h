@@ -1,5 +1,5 @@
-// Support kernels: particle binning (counting sort by scene and Morton cell
-// order), permutation of states between the caller's order and the sorted
+// Support kernels: particle binning (cell counts and a stable radix sort by
+// scene and Morton cell order), permutation of states between the caller's order and the sorted
 // internal order, the mean-position loss and its seed, the open-loop
 // actuation signal and its adjoint, and buffer clears.
 #pragma once
@@ -115,31 +115,61 @@ __global__ void k_scan_add(int* out, long n, const int* sums) {
     if (base + j < n) out[base + j] += add;
 }
 
-// perm[start[key] + rank] = i, with rank taken from a running counter.
-__global__ void k_sort_scatter(const unsigned* keys, int N, const int* start, int* fill, int* perm) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const unsigned key = keys[i];
-  const int pos = start[key] + atomicAdd(fill + key, 1);
-  perm[pos] = i;
+// Stable least-significant-digit radix sort of (key, index) pairs, 8 bits
+// per pass, tiles of kRadixTile consecutive elements (one per thread). A pass
+// counts each tile's digits (k_radix_hist, digit-major so that one exclusive
+// scan gives every (digit, tile) its output offset), then each tile writes
+// its elements in index order within every digit (k_radix_scatter: the rank
+// among same-digit lanes of a wave comes from eight ballots, the waves of the
+// tile follow each other). Equal keys therefore keep their caller order, and
+// the work per element is the same whatever the key distribution (a single
+// key holding every particle included).
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kRadixTile = 256;
+
+__global__ void __launch_bounds__(kRadixTile) k_radix_hist(const unsigned* keys, int N, int shift, int n_tiles,
+                                                           int* hist) {
+  __shared__ int cnt[kRadix];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int i = blockIdx.x * kRadixTile + int(threadIdx.x);
+  if (i < N) atomicAdd(&cnt[(keys[i] >> shift) & (kRadix - 1)], 1);
+  __syncthreads();
+  hist[long(threadIdx.x) * n_tiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Orders each key's run of perm by particle index, so the sorted order does
-// not depend on atomic arrival order.
-__global__ void k_sort_fixup(int* perm, const int* start, long n_keys, int N) {
-  const long key = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (key >= n_keys) return;
-  const int lo = start[key];
-  const int hi = (key + 1 < n_keys) ? start[key + 1] : N;
-  for (int a = lo + 1; a < hi; ++a) {
-    const int v = perm[a];
-    int b = a - 1;
-    while (b >= lo && perm[b] > v) {
-      perm[b + 1] = perm[b];
-      --b;
-    }
-    perm[b + 1] = v;
+// offs: exclusive scan of hist. vin null: the values are the element indices.
+__global__ void __launch_bounds__(kRadixTile) k_radix_scatter(const unsigned* kin, const int* vin, int N, int shift,
+                                                              int n_tiles, const int* offs, unsigned* kout,
+                                                              int* vout) {
+  constexpr int kWaves = kRadixTile / 64;
+  __shared__ int wcnt[kWaves][kRadix];
+  const int t = int(threadIdx.x), w = t >> 6, lane = t & 63;
+  for (int q = t; q < kWaves * kRadix; q += kRadixTile) (&wcnt[0][0])[q] = 0;
+  const int i = blockIdx.x * kRadixTile + t;
+  const bool live = i < N;
+  const unsigned key = live ? kin[i] : 0u;
+  const int d = int((key >> shift) & (kRadix - 1));
+  unsigned long long same = __ballot(live);
+#pragma unroll
+  for (int b = 0; b < kRadixBits; ++b) {
+    const bool bit = (d >> b) & 1;
+    const unsigned long long m = __ballot(bit);
+    same &= bit ? m : ~m;
   }
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int rank = __popcll(same & below);
+  const int group = __popcll(same);
+  __syncthreads();  // wcnt cleared
+  if (live && rank == group - 1) wcnt[w][d] = group;
+  __syncthreads();
+  if (!live) return;
+  int before = 0;
+  for (int q = 0; q < w; ++q) before += wcnt[q][d];
+  const int pos = offs[long(d) * n_tiles + blockIdx.x] + before + rank;
+  kout[pos] = key;
+  vout[pos] = vin ? vin[i] : i;
 }
 
 // Workgroup partition aligned to the Morton cell hierarchy, built from the
@@ -276,6 +306,11 @@ __global__ void k_scatter_state(StateRef src, StateRef dst, const int* perm, int
     dst.C[c * dst.stride + j] = src.C[c * src.stride + i];
     dst.F[c * dst.stride + j] = src.F[c * src.stride + i];
   }
+}
+
+__global__ void k_copy_i4(const int4* src, int4* dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 __global__ void k_gather_i32(const int* src, int* dst, const int* perm, int N) {

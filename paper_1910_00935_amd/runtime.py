@@ -150,6 +150,13 @@ class Simulator:
     def tape(self, n_steps: int, ckpt_every: int = 0) -> "Tape":
         return Tape(self, n_steps, ckpt_every)
 
+    def sort_order(self, state: State) -> torch.Tensor:
+        """The order in which a tape keeps the particles of `state`: int32 [N],
+        entry j = caller index of the j-th particle (mpm_sort_order)."""
+        perm = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        L.mpm_sort_order(self.ctx, state.c(), perm.data_ptr(), _stream())
+        return perm
+
     def loss_mean(self, final: State, axis: int, sign: float = 1.0, seed: Optional[State] = None):
         loss = torch.empty(self.n_scenes, device=self.device)
         L.mpm_loss(self.ctx, L.MPM_LOSS_MEAN_POS, axis, sign, final.c(), loss.data_ptr(),
@@ -179,6 +186,7 @@ class Tape:
         self.n_steps = int(n_steps)
         self.ckpt_every = int(ckpt_every)
         self.h = L.mpm_tape_create(sim.ctx, self.n_steps, self.ckpt_every)
+        self.generation = 0  # forwards run on this tape (each replaces the recorded trajectory)
         self.nbytes = L.mpm_tape_bytes(self.h)
         self.mem = _dev_bytes(self.nbytes, sim.device)
         L.mpm_tape_bind(self.h, self.mem.data_ptr(), self.nbytes)
@@ -191,6 +199,7 @@ class Tape:
 
     def forward(self, params: Params, init: State, final: State):
         L.mpm_tape_forward(self.h, params.c(), init.c(), final.c(), _stream())
+        self.generation += 1
 
     def backward(self, params: Params, final_grad: State, init_grad: State, gE: Optional[torch.Tensor] = None,
                  gact: Optional[torch.Tensor] = None):
@@ -217,21 +226,26 @@ def state_for_scene(scene, device="cuda") -> State:
 class MPMTrajectory(torch.autograd.Function):
     """Differentiable trajectory: (x0, v0, C0, F0, E, act) -> (xT, vT, CT, FT).
 
+    ``params`` supplies the parameters that are not differentiated (nu, vol,
+    rho, act_id, mat_id); its E and act are replaced by the E and act inputs.
     The forward runs the tape; the backward replays it in reverse (with
     segment recompute when the tape is checkpointed) and returns gradients for
-    the initial state, E and the actuation table."""
+    the initial state, E and the actuation table. A tape records one
+    trajectory: if it is run forward again before this trajectory's backward,
+    the backward raises instead of returning another trajectory's gradients."""
 
     @staticmethod
-    def forward(ctx, tape: Tape, x0, v0, C0, F0, E, nu, vol, rho, act_id, act):
+    def forward(ctx, tape: Tape, params: Params, x0, v0, C0, F0, E, act):
         sim = tape.sim
-        params = Params(E.detach().contiguous(), nu.detach().contiguous(), vol.detach().contiguous(),
-                        rho.detach().contiguous(), act_id, None if act is None else act.detach().contiguous())
+        p = Params(E.detach().contiguous(), params.nu, params.vol, params.rho, params.act_id,
+                   None if act is None else act.detach().contiguous(), params.mat_id)
         init = State(x0.detach().contiguous(), v0.detach().contiguous(), C0.detach().contiguous(),
                      F0.detach().contiguous())
         final = State.empty(sim.dim, sim.N, sim.device)
-        tape.forward(params, init, final)
+        tape.forward(p, init, final)
         ctx.tape = tape
-        ctx.params = params
+        ctx.generation = tape.generation
+        ctx.params = p
         ctx.init = init
         ctx.has_act = act is not None
         return final.x, final.v, final.C, final.F
@@ -239,6 +253,9 @@ class MPMTrajectory(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gx, gv, gC, gF):
         tape, sim = ctx.tape, ctx.tape.sim
+        if tape.generation != ctx.generation:
+            raise RuntimeError("the tape of this trajectory was run forward again before its backward; "
+                               "use one tape per trajectory that is differentiated")
 
         def z(g, like):
             return torch.zeros_like(like) if g is None else g.contiguous()
@@ -248,7 +265,7 @@ class MPMTrajectory(torch.autograd.Function):
         gE = torch.zeros_like(ctx.params.E)
         gact = torch.zeros_like(ctx.params.act) if ctx.has_act else None
         tape.backward(ctx.params, fg, ig, gE, gact)
-        return (None, ig.x, ig.v, ig.C, ig.F, gE, None, None, None, None, gact)
+        return (None, None, ig.x, ig.v, ig.C, ig.F, gE, gact)
 
 
 class Actuation(torch.autograd.Function):
@@ -270,6 +287,7 @@ class Actuation(torch.autograd.Function):
 
 
 def trajectory(tape: Tape, init: State, params: Params, act: Optional[torch.Tensor] = None):
-    """Differentiable final state of `tape.n_steps` steps."""
-    return MPMTrajectory.apply(tape, init.x, init.v, init.C, init.F, params.E, params.nu, params.vol, params.rho,
-                               params.act_id, act)
+    """Differentiable final state of `tape.n_steps` steps (all of `params`,
+    material ids included, reach the tape; E and act are differentiated)."""
+    return MPMTrajectory.apply(tape, params, init.x, init.v, init.C, init.F, params.E,
+                               params.act if act is None else act)

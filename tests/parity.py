@@ -3,6 +3,11 @@
 inputs, and compare with the tolerances of the parity gates:
   x after the gated horizon: ||x_gpu - x_orc|| / ||x_orc|| <= 1e-4;
   gradients: cosine >= 0.999 and ||g_gpu - g_orc|| / ||g_orc|| <= 1e-3.
+Norm gates over many particles cannot see one particle that is far off, so
+each comparison also gates per particle:
+  max_p |x_gpu,p - x_orc,p| / dx <= 1e-2 (one hundredth of a cell);
+  max_p |g_gpu,p - g_orc,p| / rms_p |g_orc,p| <= 5e-2 for each gradient tensor
+  (|.| the particle's block, e.g. its 3 x 3 dL/dF).
 """
 from __future__ import annotations
 
@@ -18,6 +23,8 @@ from paper_1910_00935_amd import runtime as rt
 X_REL = 1e-4
 G_COS = 0.999
 G_REL = 1e-3
+X_MAX_CELLS = 1e-2
+G_MAX_RMS = 5e-2
 
 
 def log(msg):
@@ -39,6 +46,27 @@ def cos(a, b):
     if na == 0 and nb == 0:
         return 1.0
     return float(a @ b / (na * nb))
+
+
+def max_dx_cells(a, b, dx):
+    """Largest per-particle position error, in cells."""
+    d = np.asarray(a, np.float64) - np.asarray(b, np.float64)
+    return float(np.sqrt((d.reshape(d.shape[0], -1) ** 2).sum(1)).max() / dx) if d.size else 0.0
+
+
+def max_rms(a, b):
+    """Largest per-particle error of a gradient tensor over the RMS of the
+    reference's per-particle norms (0 when both are zero)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    n = a.shape[0]
+    if n == 0:
+        return 0.0
+    err = np.sqrt(((a - b).reshape(n, -1) ** 2).sum(1))
+    rms = np.sqrt(((b.reshape(n, -1) ** 2).sum(1)).mean())
+    if rms == 0.0:
+        return 0.0 if err.max() == 0.0 else float("inf")
+    return float(err.max() / rms)
 
 
 def act_table(scene, T):
@@ -102,19 +130,22 @@ def compare(name, scene, g, o, grads=("v",), check_E=True, x_rel=X_REL):
     """Asserts the parity gates; returns the measured figures."""
     x0 = scene.x.astype(np.float64)
     xg, xo = g["final"][0], o["final"][0]
-    r = {"x_rel": rel(xg, xo), "disp_rel": rel(xg - x0, xo - x0)}
+    r = {"x_rel": rel(xg, xo), "disp_rel": rel(xg - x0, xo - x0), "x_max_cells": max_dx_cells(xg, xo, scene.dx)}
     names = dict(x=0, v=1, C=2, F=3)
     for k in grads:
         gg, go = g["g0"][names[k]], o["g0"][names[k]]
         r[f"g{k}_cos"] = cos(gg, go)
         r[f"g{k}_rel"] = rel(gg, go)
+        r[f"g{k}_max_rms"] = max_rms(gg, go)
     if check_E:
         r["gE_rel"] = rel(g["gE"], o["gE"])
     log(f"[parity] {name}: " + ", ".join(f"{k}={v:.3g}" for k, v in r.items()))
     assert g["flags"] == 0 and o["err"] == 0, (g["flags"], o["err"])
     assert r["x_rel"] <= x_rel, r
+    assert r["x_max_cells"] <= X_MAX_CELLS, r
     for k in grads:
         assert r[f"g{k}_cos"] >= G_COS and r[f"g{k}_rel"] <= G_REL, (k, r)
+        assert r[f"g{k}_max_rms"] <= G_MAX_RMS, (k, r)
     if check_E:
         assert r["gE_rel"] <= G_REL, r
     return r

@@ -2,8 +2,11 @@
 configuration the benchmark uses, plus properties that hold at any size:
   actuated2d  2D actuated soft body, 512 steps: W, b gradients through the actuation;
   elastic3d  3D, full 256-step horizon;
-  elastic3d_long  3D 128^3, 262144 particles: checkpointed tape vs oracle on a short
-      horizon, and K=64 vs full tape over all 1024 steps (GPU only);
+  elastic3d_long  3D 128^3, 262144 particles: x against the oracle after 64 and 128
+      steps; each 32-step reverse segment of a 128-step trajectory, started on
+      the GPU from the oracle's state; the whole 128-step gradient with
+      checkpoints every 64 (two segments) and every 32 (four segments, so the
+      recompute ring is reused); K=64 vs full tape over all 1024 steps (GPU only);
   batched2d  256 batched scenes, 256 steps: sampled scenes vs the oracle one by one,
       and batch vs per-scene runs of the same scenes on the GPU.
 """
@@ -17,7 +20,8 @@ import oracle as orc
 from paper_1910_00935_amd import runtime as rt
 from paper_1910_00935_amd import scenes
 
-from parity import G_COS, G_REL, X_REL, act_table, compare, cos, gpu_run, log, oracle_run, random_seed, rel
+from parity import (G_COS, G_MAX_RMS, G_REL, X_MAX_CELLS, X_REL, act_table, compare, cos, gpu_run, log, max_dx_cells,
+                    max_rms, oracle_run, random_seed, rel)
 
 pytestmark = pytest.mark.gpu
 
@@ -69,6 +73,112 @@ def test_elastic3d_long_full_size_short_horizon():
     o = oracle_run(sc, 8, K=2, seed=w)
     log(f"  oracle {o['seconds']:.1f} s")
     compare("elastic3d_long@8 K=2", sc, g, o, grads=("x", "v", "C", "F"))
+
+
+# Oracle states and gradients of elastic3d_long over 128 steps, kept for the
+# tests below and computed in pieces of at most 32 steps, so that no test runs
+# the oracle for much more than a minute. The gradient is that of a seeded
+# random linear functional of state 128 (which depends on E; the mean-x loss
+# does not before the floor is reached).
+C4_T = 128
+C4_CHUNK = 32
+_C4 = {}
+
+
+def _c4():
+    if not _C4:
+        sc = scenes.elastic3d_long().with_steps(C4_T, ckpt_every=64)
+        w = random_seed(sc, 17)
+        _C4.update(scene=sc, w=w, states={0: orc.pack(sc.x, sc.v, sc.C, sc.F)}, grads={C4_T: (w, 0.0)})
+    return _C4
+
+
+def _c4_state(step):
+    c = _c4()
+    st = c["states"]
+    s = max(k for k in st if k <= step)
+    while s < step:
+        t = min(step - s, C4_CHUNK)
+        nxt, _, err = orc.run_fwd(c["scene"], t, st[s])
+        assert err == 0
+        st[s + t] = nxt
+        s += t
+        log(f"  oracle state {s}")
+    return st[step]
+
+
+def _c4_grad(step):
+    """(dL/dstate(step), dL/dE accumulated over steps step .. C4_T - 1)."""
+    c = _c4()
+    g = c["grads"]
+    s = min(k for k in g if k >= step)
+    while s > step:
+        t = min(s - step, C4_CHUNK)
+        g0, gE, _, err = orc.run_bwd(c["scene"], t, t, _c4_state(s - t), g[s][0])
+        assert err == 0
+        g[s - t] = (g0, g[s][1] + gE[0])
+        s -= t
+        log(f"  oracle gradient {s}")
+    return g[step]
+
+
+def _x_gate(name, sc, xg, xo):
+    r = {"x_rel": rel(xg, xo), "x_max_cells": max_dx_cells(xg, xo, sc.dx)}
+    log(f"[parity] {name}: " + ", ".join(f"{k}={v:.3g}" for k, v in r.items()))
+    assert r["x_rel"] <= X_REL and r["x_max_cells"] <= X_MAX_CELLS, r
+
+
+@pytest.mark.parametrize("T", [64, C4_T])
+def test_elastic3d_long_x_gate(T):
+    """All 262144 particles on the 128^3 grid: x after 64 steps (the gated
+    horizon) and after 128 steps, tape checkpointed every 64 steps."""
+    sc = _c4()["scene"]
+    g = gpu_run(sc, T, K=64, backward=False)
+    assert g["flags"] == 0
+    _x_gate(f"elastic3d_long x@{T} K=64", sc, g["final"][0], orc.unpack(_c4_state(T), 3)[0])
+
+
+@pytest.mark.parametrize("start", [96, 64, 32, 0])
+def test_elastic3d_long_reverse_segment(start):
+    """One 32-step segment of the 128-step reverse pass at full size: the GPU
+    tape runs from the oracle's state at `start` (rounded to FP32) and is
+    seeded with the oracle's dL/dstate(start + 32); dL/dstate(start) and the
+    segment's dL/dE are gated against the oracle's."""
+    c = _c4()
+    sc = c["scene"]
+    gN, eN = _c4_grad(start + C4_CHUNK)
+    g0, e0 = _c4_grad(start)
+    x, v, C, F = orc.unpack(_c4_state(start), 3)
+    seg = replace(sc, x=x.astype(np.float32), v=v.astype(np.float32), C=C.astype(np.float32),
+                  F=F.astype(np.float32))
+    g = gpu_run(seg, C4_CHUNK, K=0, seed=gN.astype(np.float32).astype(np.float64))
+    assert g["flags"] == 0
+    o = orc.unpack(g0, 3)
+    r = {}
+    for k, name in enumerate("xvCF"):
+        r[f"g{name}_cos"] = cos(g["g0"][k], o[k])
+        r[f"g{name}_rel"] = rel(g["g0"][k], o[k])
+        r[f"g{name}_max_rms"] = max_rms(g["g0"][k], o[k])
+    r["gE_rel"] = abs(g["gE"][0] - (e0 - eN)) / abs(e0 - eN)
+    log(f"[parity] elastic3d_long reverse {start + C4_CHUNK}->{start}: " + ", ".join(f"{k}={v:.3g}" for k, v in r.items()))
+    for name in "xvCF":
+        assert r[f"g{name}_cos"] >= G_COS and r[f"g{name}_rel"] <= G_REL and r[f"g{name}_max_rms"] <= G_MAX_RMS, (name, r)
+    assert r["gE_rel"] <= G_REL, r
+
+
+@pytest.mark.parametrize("K", [64, 32])
+def test_elastic3d_long_gradient_128(K):
+    """The whole 128-step reverse pass at full size from state 0, with the
+    tape checkpointed every K steps (K = 32: four segments, so the ring of
+    recomputed states is reused), against the oracle: x after 128 steps and
+    the gradients of the random functional with respect to x, v, C, F of
+    state 0 and E."""
+    c = _c4()
+    sc = c["scene"]
+    g0, e0 = _c4_grad(0)
+    o = {"final": orc.unpack(_c4_state(C4_T), 3), "g0": orc.unpack(g0, 3), "gE": np.array([e0]), "err": 0}
+    g = gpu_run(sc, C4_T, K=K, seed=c["w"])
+    compare(f"elastic3d_long@{C4_T} K={K} random functional", sc, g, o, grads=("x", "v", "C", "F"))
 
 
 def test_elastic3d_long_checkpointed_equals_full_tape():
@@ -159,7 +269,7 @@ def test_autograd_trajectory_matches_tape_api():
     v0 = init.v.clone().requires_grad_(True)
     E = p.E.clone().requires_grad_(True)
     tape = sim.tape(32)
-    xT, vT, CT, FT = rt.MPMTrajectory.apply(tape, x0, v0, init.C, init.F, E, p.nu, p.vol, p.rho, None, None)
+    xT, vT, CT, FT = rt.MPMTrajectory.apply(tape, p, x0, v0, init.C, init.F, E, None)
     loss = xT[0].mean() + 0.3 * (FT[0, 0] * FT[1, 1]).sum() / sc.n_particles
     loss.backward()
     ref = oracle_run(sc, 32, backward=False)
