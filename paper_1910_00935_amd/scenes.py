@@ -24,6 +24,9 @@ benchmark used a 2D scene with 6.4K particles whose grid is not stated):
   coupled3d   robot3d beside 13000 particles of weakly compressible liquid, two-way
        coupled through the grid (the robot-and-liquid setting of Appendix E.1)
   fd8  8 particles with random C and F, for finite-difference checks
+
+and the incompressible smoke simulator of Section 4.2 (SmokeScene, smoke()):
+  smoke110   periodic 110^2 grid, 100 steps, 6 Jacobi iterations per projection
 """
 from __future__ import annotations
 
@@ -367,6 +370,64 @@ def random_state(scene: Scene, seed: int, c_scale: float = 1.0, f_scale: float =
     return replace(scene, v=_f32(rng.normal(0, v_scale, (N, d))),
                    C=_f32(rng.normal(0, c_scale, (N, d, d))),
                    F=_f32(np.eye(d) + f_scale * rng.normal(0, 1, (N, d, d))))
+
+
+@dataclass
+class SmokeScene:
+    """Inputs of the incompressible smoke simulator (Section 4.2): a periodic
+    n x n grid, velocities in cells per step (axis-0 and axis-1 components),
+    a smoke density and the target density of the loss."""
+    name: str
+    n: int
+    steps: int
+    iters: int                   # Jacobi iterations per pressure projection
+    u0: np.ndarray               # float32 (n, n)
+    u1: np.ndarray               # float32 (n, n)
+    s: np.ndarray                # float32 (n, n)
+    target: np.ndarray           # float32 (n, n)
+
+    def with_steps(self, steps: int, iters: Optional[int] = None) -> "SmokeScene":
+        return replace(self, steps=int(steps), iters=self.iters if iters is None else int(iters))
+
+
+def _periodic_modes(rng, n, kmax, rms):
+    """A smooth periodic field: random low Fourier modes (|k| <= kmax per
+    axis), scaled to the given RMS."""
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    f = np.zeros((n, n))
+    for k0 in range(-kmax, kmax + 1):
+        for k1 in range(-kmax, kmax + 1):
+            if (k0, k1) != (0, 0):
+                f += rng.normal() * np.cos(2 * np.pi * (k0 * i + k1 * j) / n + rng.uniform(0, 2 * np.pi))
+    return f * (rms / np.sqrt(np.mean(f * f)))
+
+
+def _blobs(rng, n, count, radius):
+    """Density in [0, 1]: periodic Gaussian blobs at random centres."""
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    f = np.zeros((n, n))
+    for _ in range(count):
+        c0, c1 = rng.uniform(0, n, 2)
+        d0 = np.minimum(np.abs(i - c0), n - np.abs(i - c0))
+        d1 = np.minimum(np.abs(j - c1), n - np.abs(j - c1))
+        f += np.exp(-(d0 ** 2 + d1 ** 2) / (2 * (radius * n) ** 2))
+    return np.clip(f, 0.0, 1.0)
+
+
+def smoke(n: int = 110, steps: int = 100, iters: int = 6, seed: int = 7, speed: float = 0.5) -> SmokeScene:
+    """The smoke benchmark's shape (Table 2: a 110 x 110 grid, 100 steps, 6
+    Jacobi iterations per projection); the paper's initial image and target
+    pattern are not available, so the smoke is a few seeded Gaussian blobs,
+    the initial velocity a smooth random periodic field with RMS `speed`
+    cells per step (its largest values about three times that), and the
+    target another set of blobs."""
+    rng = np.random.default_rng(seed)
+    u0 = _periodic_modes(rng, n, 3, speed)
+    u1 = _periodic_modes(rng, n, 3, speed)
+    s = _blobs(rng, n, 6, 0.08)
+    target = _blobs(rng, n, 4, 0.12)
+    return SmokeScene(name=f"smoke{n}", n=n, steps=steps, iters=iters, u0=_f32(u0), u1=_f32(u1), s=_f32(s),
+                      target=_f32(target))
 
 
 REGISTRY = {"translate2d": translate2d, "deform2d": deform2d, "actuated2d": actuated2d, "elastic3d": elastic3d, "elastic3d_long": elastic3d_long, "batched2d": batched2d,
