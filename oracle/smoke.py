@@ -35,6 +35,8 @@ The adjoint of every stage is written by hand and accumulates: for a primal
 f(X) = Y the adjoint takes (X, Y*) and returns X* = dL/dX. Arrays may be
 complex: the forward map then carries complex-step tangents (the cell index
 of a sample is taken from the real part), which is how the adjoint is pinned.
+The one decision floating point makes for an integer here, the cell a
+back-traced point falls in, is taken in single precision (_sample_points).
 
 Arrays are (n, n), axis 0 first; a velocity is the pair (u0, u1).
 """
@@ -48,13 +50,18 @@ import numpy as np
 # ---------------------------------------------------------------------------
 def _sample_points(u0, u1):
     """Cell indices (a, b) of the lower corner and fractions (fa, fb) of the
-    back-traced point c - u(c) of every cell c."""
+    back-traced point c - u(c) of every cell c. Which cell a point falls in
+    is decided in single precision, the precision of the paper's GPU runs
+    (Table 2) and of the kernels: floor(fl32(c - fl32(u))). Within rounding
+    of a cell boundary the fraction may then lie a rounding error outside
+    [0, 1); the bilinear form is continuous there, and both sides take the
+    same cell, hence the same derivative of the sample."""
     n = u0.shape[0]
     i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
     y0 = i - u0
     y1 = j - u1
-    a = np.floor(np.real(y0)).astype(np.int64)
-    b = np.floor(np.real(y1)).astype(np.int64)
+    a = np.floor(i.astype(np.float32) - np.real(u0).astype(np.float32)).astype(np.int64)
+    b = np.floor(j.astype(np.float32) - np.real(u1).astype(np.float32)).astype(np.int64)
     return a, b, y0 - a, y1 - b
 
 
