@@ -205,6 +205,30 @@ mpm_status mpm_kernel_stats(mpm_ctx* ctx, int32_t kernel, double* total_ms, int6
 mpm_status mpm_step_fwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, const mpm_state* in,
                         mpm_state* out, void* stream);
 
+/* mpm_step_fwd for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, and harnesses that forbid
+ * allocation. Same step, same kernels and launch shape, same arguments, plus
+ * err_flags; the context needs no bound workspace (a context from mpm_init
+ * alone will do). Instead of the workspace, the step uses a fixed device
+ * array inside the library, 64 MiB per GPU, allocated when the library's
+ * code is loaded on that GPU and held until the process ends: it holds the
+ * grid (n_scenes * n_grid^dim * 16 bytes) and, for several scenes, the
+ * workgroup table (16 bytes per workgroup). MPM_E_CAPACITY, before any GPU
+ * work, when those exceed 64 MiB (one 160^3 grid, 62.5 MiB, fits; 170^3 does not).
+ * Allocates nothing: no hipMalloc or hipFree, no allocating library call.
+ * The array of the current device is used (the stream must belong to it);
+ * its address is looked up on the first call per device. Every call on one
+ * GPU, from any context, shares that GPU's array and leaves its content
+ * behind; each call clears the grid it uses. Calls that overlap on one GPU
+ * (other streams, other host threads) race on the array and must be
+ * serialised by the caller.
+ *   err_flags  device uint32, caller-owned: MPM_FLAG_* bits of particles
+ *              that left the grid, were inverted or not finite are OR-ed in
+ *              (the caller clears it); MPM_E_ARG if null.
+ * The knob "timing" is ignored by this call. */
+mpm_status mpm_step_fwd_noalloc(mpm_ctx* ctx, const mpm_params* params, int32_t step, const mpm_state* in,
+                                mpm_state* out, uint32_t* err_flags, void* stream);
+
 /* Adjoint of one step (Appendix D.1): recomputes the grid from `in`, then
  * replays g2p*, grid_op*, p2g*; given out_grad = dL/d(state step+1) it ADDS
  * dL/d(state step) into in_grad and dL/dE, dL/da(step) into pg. */

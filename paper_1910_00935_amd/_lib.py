@@ -73,6 +73,8 @@ _SIGNATURES = {
     "mpm_set_knob": (c_int32, [c_void_p, ctypes.c_char_p, ctypes.c_int64]),
     "mpm_step_fwd": (c_int32, [c_void_p, ctypes.POINTER(mpm_params), c_int32, ctypes.POINTER(mpm_state),
                                ctypes.POINTER(mpm_state), c_void_p]),
+    "mpm_step_fwd_noalloc": (c_int32, [c_void_p, ctypes.POINTER(mpm_params), c_int32, ctypes.POINTER(mpm_state),
+                                       ctypes.POINTER(mpm_state), c_void_p, c_void_p]),
     "mpm_step_bwd": (c_int32, [c_void_p, ctypes.POINTER(mpm_params), c_int32, ctypes.POINTER(mpm_state),
                                ctypes.POINTER(mpm_state), ctypes.POINTER(mpm_state),
                                ctypes.POINTER(mpm_param_grad), c_void_p]),
@@ -157,6 +159,11 @@ def mpm_step_fwd(ctx, params, step, st_in, st_out, stream):
          c_void_p(stream))
 
 
+def mpm_step_fwd_noalloc(ctx, params, step, st_in, st_out, err_flags, stream):
+    call("mpm_step_fwd_noalloc", ctx, ctypes.byref(params), int(step), ctypes.byref(st_in), ctypes.byref(st_out),
+         c_void_p(err_flags), c_void_p(stream))
+
+
 def mpm_step_bwd(ctx, params, step, st_in, out_grad, in_grad, pg, stream):
     call("mpm_step_bwd", ctx, ctypes.byref(params), int(step), ctypes.byref(st_in), ctypes.byref(out_grad),
          ctypes.byref(in_grad), ctypes.byref(pg), c_void_p(stream))
@@ -219,3 +226,4 @@ def mpm_check_errors(ctx, stream):
     flags = ctypes.c_uint32(0)
     st = lib().mpm_check_errors(ctx, c_void_p(stream), ctypes.byref(flags))
     return st, int(flags.value)
+

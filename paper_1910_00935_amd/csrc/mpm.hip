@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -61,6 +62,14 @@ static_assert(kNumGrids == 10, "mpm_ctx::gstate lists one initial state per grid
 
 }  // namespace
 
+// Device memory of the allocation-free forward step (mpm_step_fwd_noalloc):
+// one fixed array per GPU the library runs on, held until the process ends.
+// Host code never uses the array's name as an address (on the host it is a
+// stand-in, not device memory): each device's address is looked up once,
+// with that device current, by scratch_on_current_device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 struct mpm_ctx {
   int d = 0, n = 0, bound = 0, ns = 0, n_act = 0, N = 0, Np = 0, S = 0;
   long nodes = 0;
@@ -83,6 +92,10 @@ struct mpm_ctx {
   int model = 0;     // constitutive model: 0 neo-Hookean, 1 fixed-corotated (MPM_MODEL_COROTATED)
   int n_blocks = 0;  // workgroups per particle pass for the current block and lanes
   int n_plain = 0;   // workgroups of the plain partition
+  // Host copy of the caller-order workgroup table of single steps (R_BLOCKS:
+  // the plain partition padded to n_blocks entries), empty when the launch
+  // needs none (one scene, plain partition).
+  std::vector<int4> blocks_host;
   long blocks_cap = 0;
   // What each grid holds, tracked while a launch sequence is enqueued: kZero,
   // kDirty (anything), or n >= 0: non-zero only inside the boxes its last
@@ -188,8 +201,11 @@ StateRef user_ref(const mpm_ctx& c, const mpm_state* s) {
 }
 
 // `tp` non-null: the launch runs on that tape's sorted particle order (its
-// per-particle ids and workgroup table) rather than the caller's.
-StepConsts consts(const mpm_ctx& c, const mpm_params* p, const mpm_tape* tp) {
+// per-particle ids and workgroup table) rather than the caller's. `table` and
+// `err` are the caller-order workgroup table and the error word of the memory
+// the launch uses (the bound workspace, or the fixed scratch of the
+// allocation-free step).
+StepConsts consts(const mpm_ctx& c, const mpm_params* p, const mpm_tape* tp, const int4* table, unsigned* err) {
   const int* act_id = p->act_id ? (tp ? tp->act_ids() : p->act_id) : nullptr;
   StepConsts k;
   k.N = c.N;
@@ -207,7 +223,7 @@ StepConsts consts(const mpm_ctx& c, const mpm_params* p, const mpm_tape* tp) {
   k.lds = c.lds;
   k.remap = c.remap;
   k.rotate = c.rotate;
-  k.blocks = (c.ns > 1 || c.part) ? (tp ? tp->blocks() : c.at<int4>(R_BLOCKS)) : nullptr;
+  k.blocks = (c.ns > 1 || c.part) ? (tp ? tp->blocks() : table) : nullptr;
   k.n_blocks = c.n_blocks;
   k.E = p->E;
   k.nu = p->nu;
@@ -215,8 +231,12 @@ StepConsts consts(const mpm_ctx& c, const mpm_params* p, const mpm_tape* tp) {
   k.rho = p->rho;
   k.act_id = (c.n_act > 0) ? act_id : nullptr;
   k.mat_id = p->mat_id ? (tp ? tp->mat_ids() : p->mat_id) : nullptr;
-  k.err = c.at<unsigned>(R_ERR);
+  k.err = err;
   return k;
+}
+
+StepConsts consts(const mpm_ctx& c, const mpm_params* p, const mpm_tape* tp) {
+  return consts(c, p, tp, c.at<int4>(R_BLOCKS), c.at<unsigned>(R_ERR));
 }
 
 // Geometry of the cell hierarchy for the aligned partition (P particles per
@@ -347,8 +367,8 @@ struct SpanGuard {
 };
 
 template <int D, int LPP>
-mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& args, hipStream_t st) {
-  span_step(c, 0, st);
+mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& args, hipStream_t st, bool timed) {
+  if (timed) span_step(c, 0, st);
   FwdArgs a = args;
   a.k.threads = c.block;
   a.k.clear_per_role = c.part ? c.n_plain : c.n_blocks;
@@ -377,13 +397,14 @@ mpm_status launch_bwd(const mpm_ctx& c, const BwdArgs& args, hipStream_t st) {
   return MPM_OK;
 }
 
-mpm_status fwd(const mpm_ctx& c, const FwdArgs& a, hipStream_t st) {
+// `timed`: the launch may take part in the "timing" knob's event spans.
+mpm_status fwd(const mpm_ctx& c, const FwdArgs& a, hipStream_t st, bool timed = true) {
   if (c.d == 2) {
-    if (c.lanes == 4) return launch_fwd<2, 4>(c, a, st);
-    return c.lanes == 2 ? launch_fwd<2, 2>(c, a, st) : launch_fwd<2, 1>(c, a, st);
+    if (c.lanes == 4) return launch_fwd<2, 4>(c, a, st, timed);
+    return c.lanes == 2 ? launch_fwd<2, 2>(c, a, st, timed) : launch_fwd<2, 1>(c, a, st, timed);
   }
-  if (c.lanes == 4) return launch_fwd<3, 4>(c, a, st);
-  return c.lanes == 2 ? launch_fwd<3, 2>(c, a, st) : launch_fwd<3, 1>(c, a, st);
+  if (c.lanes == 4) return launch_fwd<3, 4>(c, a, st, timed);
+  return c.lanes == 2 ? launch_fwd<3, 2>(c, a, st, timed) : launch_fwd<3, 1>(c, a, st, timed);
 }
 mpm_status bwd(const mpm_ctx& c, const BwdArgs& a, hipStream_t st) {
   if (c.d == 2) {
@@ -533,6 +554,26 @@ mpm_status scatter_state(const mpm_ctx& c, StateRef src, StateRef dst, const int
     if (st_ != MPM_OK) return st_;   \
   } while (0)
 
+// Device address of `scratch` on the current device, looked up with
+// hipGetSymbolAddress on the first call per device and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+mpm_status scratch_on_current_device(char** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return MPM_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MPM_E_HIP;
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return MPM_OK;
+}
+
 // Forward steps t0 .. t1-1 from state t0 (already in its slot), writing
 // states t0+1 .. t1 into their slots, using the three forward grids.
 mpm_status run_forward(mpm_tape& tp, const mpm_params* p, int t0, int t1, hipStream_t s) {
@@ -594,16 +635,57 @@ mpm_status update_blocks(mpm_ctx& c) {
   c.n_plain = int(t.size());
   if (!c.part && c.ns <= 1) {
     c.n_blocks = (c.N + per_block - 1) / per_block;
+    c.blocks_host.clear();
     return MPM_OK;
   }
   c.n_blocks = c.part ? 2 * c.n_plain + 32 : c.n_plain;
   if (c.n_blocks > c.blocks_cap || c.n_blocks > c.box_cap) return MPM_E_CAPACITY;
-  if (c.ws) {
-    HIP_TRY(hipMemcpy(c.at<int4>(R_PLAIN), t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
-    t.resize(size_t(c.n_blocks), make_int4(0, 0, 0, 0));
-    HIP_TRY(hipMemcpy(c.at<int4>(R_BLOCKS), t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
-  }
+  if (c.ws) HIP_TRY(hipMemcpy(c.at<int4>(R_PLAIN), t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
+  t.resize(size_t(c.n_blocks), make_int4(0, 0, 0, 0));
+  if (c.ws) HIP_TRY(hipMemcpy(c.at<int4>(R_BLOCKS), t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
+  c.blocks_host = std::move(t);
   return MPM_OK;
+}
+
+bool step_fwd_args_ok(const mpm_params* params, int step, const mpm_state* in, const mpm_state* out) {
+  if (!params_ok(params) || !state_ok(in) || !state_ok(out) || step < 0) return false;
+  return !(in->x == out->x || in->v == out->v || in->C == out->C || in->F == out->F);
+}
+
+// Device buffers one forward step uses besides its inputs and outputs: the
+// grid it scatters into and gathers from, the caller-order workgroup table
+// (null when the launch needs none) and the error word.
+struct StepBufs {
+  float4* grid;
+  const int4* table;
+  unsigned* err;
+};
+
+// One forward step in the caller's order: clear the grid, p2g, then grid_op
+// folded into g2p (two launches; no box records, so the grid is cleared
+// densely). `timed`: the launches may join the "timing" knob's event spans.
+mpm_status enqueue_step_fwd(const mpm_ctx& c, const mpm_params* params, int step, const mpm_state* in,
+                            mpm_state* out, const StepBufs& b, bool timed, hipStream_t s) {
+  const long n4 = c.grid_f4();
+  if (timed) span_close(c);
+  hipLaunchKernelGGL(mpm::k_zero_f4, dim3(int(std::min<long>((n4 + 255) / 256, 8192))), dim3(256), 0, s, b.grid, n4);
+  LAUNCH_TRY();
+  FwdArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.k = consts(c, params, nullptr, b.table, b.err);
+  a.in = user_ref(c, in);
+  a.grid_out = b.grid;
+  a.act_row = act_row(c, params, step);
+  a.do_p2g = 1;
+  TRY(fwd(c, a, s, timed));
+  FwdArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.k = a.k;
+  g.in = user_ref(c, in);
+  g.out = user_ref(c, out);
+  g.grid_in = b.grid;
+  g.do_g2p = 1;
+  return fwd(c, g, s, timed);
 }
 
 bool same_params(const mpm_params& a, const mpm_params* b) {
@@ -813,26 +895,32 @@ mpm_status mpm_step_fwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, co
                         void* stream) {
   if (!ctx) return MPM_E_ARG;
   if (!ctx->ws) return MPM_E_STATE;
-  if (!params_ok(params) || !state_ok(in) || !state_ok(out) || step < 0) return MPM_E_ARG;
-  if (in->x == out->x || in->v == out->v || in->C == out->C || in->F == out->F) return MPM_E_ARG;
+  if (!step_fwd_args_ok(params, step, in, out)) return MPM_E_ARG;
   const mpm_ctx& c = *ctx;
   const SpanGuard guard(c);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  float4* g = c.grid(kGridB);
-  TRY(zero_f4(c, g, c.grid_f4(), s));
   c.gstate[kGridB] = kDirty;  // written below without a box record
-  FwdArgs a = fwd_args(c, params, nullptr);
-  a.in = user_ref(c, in);
-  a.grid_out = g;
-  a.act_row = act_row(c, params, step);
-  a.do_p2g = 1;
-  TRY(fwd(c, a, s));
-  FwdArgs b = fwd_args(c, params, nullptr);
-  b.in = user_ref(c, in);
-  b.out = user_ref(c, out);
-  b.grid_in = g;
-  b.do_g2p = 1;
-  return fwd(c, b, s);
+  const StepBufs b{c.grid(kGridB), c.at<int4>(R_BLOCKS), c.at<unsigned>(R_ERR)};
+  return enqueue_step_fwd(c, params, step, in, out, b, true, static_cast<hipStream_t>(stream));
+}
+
+mpm_status mpm_step_fwd_noalloc(mpm_ctx* ctx, const mpm_params* params, int32_t step, const mpm_state* in,
+                                mpm_state* out, uint32_t* err_flags, void* stream) {
+  if (!ctx || !err_flags) return MPM_E_ARG;
+  if (!step_fwd_args_ok(params, step, in, out)) return MPM_E_ARG;
+  const mpm_ctx& c = *ctx;
+  const size_t grid_bytes = align_up(size_t(c.grid_f4()) * sizeof(float4));
+  const size_t table_bytes = c.blocks_host.size() * sizeof(int4);
+  if (grid_bytes + table_bytes > kScratchBytes) return MPM_E_CAPACITY;
+  char* base = nullptr;
+  TRY(scratch_on_current_device(&base));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int4* table = reinterpret_cast<int4*>(base + grid_bytes);
+  // The table of an earlier call (another context) may differ: upload this
+  // context's every call, stream-ordered before the launches that read it.
+  if (table_bytes) HIP_TRY(hipMemcpyAsync(table, c.blocks_host.data(), table_bytes, hipMemcpyHostToDevice, s));
+  const StepBufs b{reinterpret_cast<float4*>(base), c.blocks_host.empty() ? nullptr : table,
+                   reinterpret_cast<unsigned*>(err_flags)};
+  return enqueue_step_fwd(c, params, step, in, out, b, false, s);
 }
 
 mpm_status mpm_step_bwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, const mpm_state* in,

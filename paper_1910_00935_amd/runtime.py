@@ -106,7 +106,8 @@ class Simulator:
     """One context: a description (grid, time step, scenes) plus bound workspace."""
 
     def __init__(self, dim, n_grid, dx, dt, scene_offsets, gravity=-9.8, bound=3, n_actuators=0,
-                 act_strength=0.0, device="cuda", knobs: Optional[dict] = None, model: int = 0):
+                 act_strength=0.0, device="cuda", knobs: Optional[dict] = None, model: int = 0,
+                 workspace: bool = True):
         self.dim, self.n_grid, self.dx, self.dt = int(dim), int(n_grid), float(dx), float(dt)
         self.offsets = np.ascontiguousarray(scene_offsets, dtype=np.int32)
         self.n_scenes = len(self.offsets) - 1
@@ -118,16 +119,21 @@ class Simulator:
                           self._off_c, self.n_act, float(act_strength),
                           L.MPM_MODEL_COROTATED if model == 1 else 0)
         self.ctx = L.mpm_init(desc)
-        self.workspace = _dev_bytes(L.mpm_workspace_bytes(self.ctx), device)
-        L.mpm_bind_workspace(self.ctx, self.workspace.data_ptr(), self.workspace.numel())
+        # workspace=False: no device memory is bound; only step_fwd_noalloc
+        # (mpm_step_fwd_noalloc) can run on such a context.
+        self.workspace = None
+        if workspace:
+            self.workspace = _dev_bytes(L.mpm_workspace_bytes(self.ctx), device)
+            L.mpm_bind_workspace(self.ctx, self.workspace.data_ptr(), self.workspace.numel())
         for k, v in (knobs or {}).items():
             L.mpm_set_knob(self.ctx, k, v)
 
     @staticmethod
-    def for_scene(scene, device="cuda", knobs=None) -> "Simulator":
+    def for_scene(scene, device="cuda", knobs=None, workspace: bool = True) -> "Simulator":
         return Simulator(scene.dim, scene.n_grid, scene.dx, scene.dt, scene.offsets, gravity=scene.gravity,
                          bound=scene.bound, n_actuators=scene.n_act, act_strength=scene.act_strength,
-                         device=device, knobs=knobs, model=int(getattr(scene, "model", 0) or 0))
+                         device=device, knobs=knobs, model=int(getattr(scene, "model", 0) or 0),
+                         workspace=workspace)
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
@@ -141,6 +147,12 @@ class Simulator:
     # Single steps (caller particle order).
     def step_fwd(self, params: Params, step: int, s_in: State, s_out: State):
         L.mpm_step_fwd(self.ctx, params.c(), step, s_in.c(), s_out.c(), _stream())
+
+    def step_fwd_noalloc(self, params: Params, step: int, s_in: State, s_out: State, err_flags: torch.Tensor):
+        """mpm_step_fwd without workspace: the library's fixed device array
+        holds the grid; error bits are OR-ed into err_flags (int32 [1])."""
+        assert err_flags.dtype == torch.int32 and err_flags.is_cuda and err_flags.numel() >= 1
+        L.mpm_step_fwd_noalloc(self.ctx, params.c(), step, s_in.c(), s_out.c(), err_flags.data_ptr(), _stream())
 
     def step_bwd(self, params: Params, step: int, s_in: State, out_grad: State, in_grad: State,
                  gE: Optional[torch.Tensor] = None, gact: Optional[torch.Tensor] = None):
@@ -291,3 +303,4 @@ def trajectory(tape: Tape, init: State, params: Params, act: Optional[torch.Tens
     material ids included, reach the tape; E and act are differentiated)."""
     return MPMTrajectory.apply(tape, params, init.x, init.v, init.C, init.F, params.E,
                                params.act if act is None else act)
+
