@@ -395,6 +395,48 @@ def run_robot3d(args, torch, rt, scenes, iters=3, name="robot3d"):
             "ms_per_iteration": secs * 1e3 / iters, "losses": [round(v, 6) for v in hist], "knobs": knobs}
 
 
+def run_smoke(args, torch, rt, scenes, tile=0, repeats=10):
+    """The incompressible smoke simulator (Section 4.2, Table 2's workload:
+    110^2 periodic grid, 100 steps, 6 Jacobi iterations per projection):
+    forward trajectory, loss and seed, reverse pass, timed separately with
+    events on the launch stream; medians over `repeats` runs."""
+    import statistics
+    sc = scenes.smoke()
+    sim = rt.SmokeSim.for_scene(sc, tile=tile)
+    init = rt.smoke_state(sc)
+    target = torch.as_tensor(sc.target, device="cuda")
+    seed = torch.empty(3, sc.n, sc.n, device="cuda")
+    grad = torch.zeros(3, sc.n, sc.n, device="cuda")
+    stream = torch.cuda.current_stream()
+    fwd, bwd = [], []
+    for r in range(repeats + 2):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        sim.forward(init)
+        sim.loss(target, seed)
+        ev[1].record(stream)
+        sim.backward(seed, grad)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        if r >= 2:
+            fwd.append(ev[0].elapsed_time(ev[1]))
+            bwd.append(ev[1].elapsed_time(ev[2]))
+    if sim.check_errors():
+        raise RuntimeError("smoke: error flags set")
+    f, b = statistics.median(fwd), statistics.median(bwd)
+    cells = sc.n * sc.n * sc.steps
+    state = 3 * sc.n * sc.n * 4
+    return {"workload": f"incompressible smoke, {sc.n}^2 periodic grid, {sc.steps} steps, {sc.iters} Jacobi "
+                        f"iterations per projection, loss = sum (s_T - target)^2, gradient w.r.t. the initial state",
+            "fwd_ms": round(f, 4), "bwd_ms": round(b, 4), "total_ms": round(f + b, 4),
+            "cell_steps_per_s": cells / ((f + b) * 1e-3),
+            # Per launch: forward reads state s and writes state s+1; reverse
+            # reads states s, s+1 and the adjoint of s+1 and writes the adjoint of s.
+            "alg_bytes_per_launch": {"fwd": 2 * state, "bwd": 4 * state},
+            "launch_us": {"fwd": round(f * 1e3 / sc.steps, 3), "bwd": round(b * 1e3 / sc.steps, 3)},
+            "tile": tile or 16, "runs": repeats}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -406,6 +448,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-robot", action="store_true")
+    ap.add_argument("--no-smoke", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default launch configuration")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune.json"))
     ap.add_argument("--knobs", default=None, help='launch configuration for the 3D workload as JSON, e.g. \'{"block": 256}\'')
@@ -480,6 +523,9 @@ def main():
         out["coupled3d"] = run_robot3d(args, torch, rt, scenes, name="coupled3d")
         print("[bench] fixed-corotated model", flush=True)
         out["elastic3d_corotated"] = run_corotated(args, torch, rt, scenes, elastic3d["knobs"])
+    if not args.no_smoke:
+        print("[bench] smoke simulator", flush=True)
+        out["smoke"] = run_smoke(args, torch, rt, scenes)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", flush=True)
         out["cpu_baseline"] = run_cpu_baseline(args.cpu_sample_steps)

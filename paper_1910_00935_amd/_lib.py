@@ -55,6 +55,10 @@ class mpm_param_grad(ctypes.Structure):
     _fields_ = [("E", c_void_p), ("act", c_void_p)]
 
 
+class smoke_desc(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("steps", c_int32), ("iters", c_int32), ("tile", c_int32)]
+
+
 class MPMError(RuntimeError):
     def __init__(self, fn, status):
         self.status = status
@@ -95,6 +99,16 @@ _SIGNATURES = {
     "mpm_check_errors": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
     "mpm_kernel_stats": (c_int32, [c_void_p, c_int32, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int64)]),
+    # include/smoke.h
+    "smoke_tape_bytes": (c_size_t, [ctypes.POINTER(smoke_desc)]),
+    "smoke_workspace_bytes": (c_size_t, [ctypes.POINTER(smoke_desc)]),
+    "smoke_workspace_init": (c_int32, [ctypes.POINTER(smoke_desc), c_void_p, c_void_p]),
+    "smoke_forward": (c_int32, [ctypes.POINTER(smoke_desc), c_void_p, c_void_p, c_void_p, c_void_p]),
+    "smoke_loss": (c_int32, [ctypes.POINTER(smoke_desc), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                             c_void_p]),
+    "smoke_backward": (c_int32, [ctypes.POINTER(smoke_desc), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "smoke_check_errors": (c_int32, [ctypes.POINTER(smoke_desc), c_void_p, c_void_p,
+                                     ctypes.POINTER(ctypes.c_uint32)]),
 }
 
 
@@ -227,3 +241,34 @@ def mpm_check_errors(ctx, stream):
     st = lib().mpm_check_errors(ctx, c_void_p(stream), ctypes.byref(flags))
     return st, int(flags.value)
 
+
+def smoke_tape_bytes(desc):
+    return int(lib().smoke_tape_bytes(ctypes.byref(desc)))
+
+
+def smoke_workspace_bytes(desc):
+    return int(lib().smoke_workspace_bytes(ctypes.byref(desc)))
+
+
+def smoke_workspace_init(desc, ws, stream):
+    call("smoke_workspace_init", ctypes.byref(desc), c_void_p(ws), c_void_p(stream))
+
+
+def smoke_forward(desc, init, tape, ws, stream):
+    call("smoke_forward", ctypes.byref(desc), c_void_p(init), c_void_p(tape), c_void_p(ws), c_void_p(stream))
+
+
+def smoke_loss(desc, tape, target, loss, seed, ws, stream):
+    call("smoke_loss", ctypes.byref(desc), c_void_p(tape), c_void_p(target), c_void_p(loss), c_void_p(seed),
+         c_void_p(ws), c_void_p(stream))
+
+
+def smoke_backward(desc, tape, seed, grad, ws, stream):
+    call("smoke_backward", ctypes.byref(desc), c_void_p(tape), c_void_p(seed), c_void_p(grad), c_void_p(ws),
+         c_void_p(stream))
+
+
+def smoke_check_errors(desc, ws, stream):
+    flags = ctypes.c_uint32(0)
+    st = lib().smoke_check_errors(ctypes.byref(desc), c_void_p(ws), c_void_p(stream), ctypes.byref(flags))
+    return st, int(flags.value)

@@ -304,3 +304,52 @@ def trajectory(tape: Tape, init: State, params: Params, act: Optional[torch.Tens
     return MPMTrajectory.apply(tape, params, init.x, init.v, init.C, init.F, params.E,
                                params.act if act is None else act)
 
+
+class SmokeSim:
+    """The incompressible smoke simulator (include/smoke.h) over torch memory:
+    a tape of steps + 1 states, each a (3, n, n) float32 tensor [u0, u1, s],
+    and a workspace. Every step runs in the HIP library."""
+
+    def __init__(self, n: int, steps: int, iters: int, tile: int = 0, device="cuda"):
+        self.desc = L.smoke_desc(int(n), int(steps), int(iters), int(tile))
+        self.n, self.steps, self.iters = int(n), int(steps), int(iters)
+        self.device = device
+        nb = L.smoke_tape_bytes(self.desc)
+        if nb == 0:
+            raise ValueError(f"invalid smoke description n={n} steps={steps} iters={iters} tile={tile}")
+        self.tape = torch.empty(self.steps + 1, 3, self.n, self.n, device=device)
+        self.workspace = _dev_bytes(L.smoke_workspace_bytes(self.desc), device)
+        L.smoke_workspace_init(self.desc, self.workspace.data_ptr(), _stream())
+
+    @staticmethod
+    def for_scene(scene, tile: int = 0, device="cuda") -> "SmokeSim":
+        return SmokeSim(scene.n, scene.steps, scene.iters, tile, device)
+
+    def forward(self, init: torch.Tensor) -> torch.Tensor:
+        """Runs the trajectory from `init` (3, n, n); returns the final state (a view of the tape)."""
+        assert init.shape == (3, self.n, self.n) and init.dtype == torch.float32 and init.is_contiguous()
+        L.smoke_forward(self.desc, init.data_ptr(), self.tape.data_ptr(), self.workspace.data_ptr(), _stream())
+        return self.tape[self.steps]
+
+    def loss(self, target: torch.Tensor, seed: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """sum (s_T - target)^2 as a one-element tensor; fills `seed` with dL/d(state T) if given."""
+        loss = torch.empty(1, device=self.device)
+        L.smoke_loss(self.desc, self.tape.data_ptr(), target.contiguous().data_ptr(), loss.data_ptr(),
+                     _ptr(seed), self.workspace.data_ptr(), _stream())
+        return loss
+
+    def backward(self, seed: torch.Tensor, grad: torch.Tensor):
+        """ADDS dL/d(state 0) into grad (3, n, n) given seed = dL/d(state T)."""
+        for t in (seed, grad):
+            assert t.shape == (3, self.n, self.n) and t.dtype == torch.float32 and t.is_contiguous()
+        L.smoke_backward(self.desc, self.tape.data_ptr(), seed.data_ptr(), grad.data_ptr(),
+                         self.workspace.data_ptr(), _stream())
+
+    def check_errors(self) -> int:
+        st, flags = L.smoke_check_errors(self.desc, self.workspace.data_ptr(), _stream())
+        return flags
+
+
+def smoke_state(scene, device="cuda") -> torch.Tensor:
+    """Initial state (3, n, n) [u0, u1, s] of a SmokeScene."""
+    return torch.as_tensor(np.stack([scene.u0, scene.u1, scene.s]), dtype=torch.float32, device=device).contiguous()

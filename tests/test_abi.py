@@ -11,13 +11,14 @@ import pytest
 from paper_1910_00935_amd import _lib as L
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "mpm.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("mpm.h", "smoke.h")]
 
 
 def _declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"\b(mpm_[a-z_0-9]+)\s*\(", src)
+    names = []
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names += re.findall(r"\b((?:mpm|smoke)_[a-z_0-9]+)\s*\(", src)
     return sorted(set(names))
 
 
@@ -123,3 +124,20 @@ def test_knobs_and_status_strings():
     for code in range(9):
         assert L.status_string(code) and L.status_string(code) != "unknown status"
     assert L.status_string(99) == "unknown status"
+
+
+def test_smoke_sizes_and_refusals():
+    d = L.smoke_desc(110, 100, 6, 0)
+    assert L.smoke_tape_bytes(d) == 101 * 3 * 110 * 110 * 4
+    ws = L.smoke_workspace_bytes(d)
+    assert 3 * 3 * 110 * 110 * 4 <= ws < 3 * 3 * 110 * 110 * 4 + 4096
+    for bad in (L.smoke_desc(3, 10, 6, 0), L.smoke_desc(5000, 10, 6, 0), L.smoke_desc(16, 0, 6, 0),
+                L.smoke_desc(16, 4, 25, 0), L.smoke_desc(16, 4, -1, 0), L.smoke_desc(16, 4, 6, 12)):
+        assert L.smoke_tape_bytes(bad) == 0 and L.smoke_workspace_bytes(bad) == 0
+        # Refused on the host, before any device access.
+        assert L.lib().smoke_forward(ctypes.byref(bad), ctypes.c_void_p(256), ctypes.c_void_p(512),
+                                     ctypes.c_void_p(1024), None) == L.MPM_E_ARG
+    assert L.lib().smoke_forward(ctypes.byref(d), None, ctypes.c_void_p(512), ctypes.c_void_p(1024),
+                                 None) == L.MPM_E_ARG
+    assert L.lib().smoke_backward(ctypes.byref(d), ctypes.c_void_p(256), ctypes.c_void_p(512 + 4),
+                                  ctypes.c_void_p(768), ctypes.c_void_p(1024), None) == L.MPM_E_ARG  # misaligned
