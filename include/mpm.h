@@ -140,26 +140,33 @@ typedef struct {
   float* act;
 } mpm_param_grad;
 
-/* Status text (static string). */
+/* Status text (static string). Support call: the paper defines no error
+ * reporting. */
 const char* mpm_status_string(mpm_status s);
 
-/* Creates a context for the description. Host-only: validates the fields,
- * copies scene_offsets and sizes the workspace. MPM_E_ARG on invalid fields. */
+/* Creates a context for the description (Section 4.1's simulator: grid,
+ * time step, scenes; the paper's kernels take these as compile-time
+ * constants). Host-only: validates the fields, copies scene_offsets and sizes
+ * the workspace. MPM_E_ARG on invalid fields. */
 mpm_status mpm_init(const mpm_desc* desc, mpm_ctx** out);
 
-/* Destroys the context (host objects only; never frees caller memory). */
+/* Destroys the context (host objects only; never frees caller memory).
+ * Support call. */
 void mpm_destroy(mpm_ctx* ctx);
 
 /* Bytes of device workspace the context needs (grids, sort buffers, adjoint
- * scratch, FP64 reduction accumulators, error word); 0 for a null ctx. */
+ * scratch, FP64 reduction accumulators, error word); 0 for a null ctx.
+ * Support call (memory management; Appendix D.1 is why it holds grids for
+ * only a few steps: the reverse pass recomputes each grid). */
 size_t mpm_workspace_bytes(const mpm_ctx* ctx);
 
 /* Binds caller-owned device workspace of at least mpm_workspace_bytes bytes
  * (256-byte aligned) and initialises it (synchronously on the null stream).
- * MPM_E_CAPACITY if too small, MPM_E_ARG if misaligned. */
+ * MPM_E_CAPACITY if too small, MPM_E_ARG if misaligned. Support call. */
 mpm_status mpm_bind_workspace(mpm_ctx* ctx, void* dev, size_t bytes);
 
-/* Sets a knob: "block" (threads per workgroup of the per-particle kernels:
+/* Sets a knob (support call: launch shape and measurement switches; none
+ * changes what is computed beyond FP32 rounding order): "block" (threads per workgroup of the per-particle kernels:
  * 64, 128, 192 or 256); "lds" (0/1, default 1: stage each workgroup's stencil
  * footprint in LDS when it fits, else use global memory directly); "split"
  * (0/1, default 1: run the reverse launch's grid recompute for the previous
@@ -178,6 +185,12 @@ mpm_status mpm_bind_workspace(mpm_ctx* ctx, void* dev, size_t bytes);
  * stays compact when particle density varies; the launch then has room for
  * up to twice the plain number of workgroups, the unused ones empty; with 0,
  * workgroups are runs of consecutive sorted particles);
+ * "tile_stats" (0/1, default 0: count scatter tiles, see mpm_tile_stats);
+ * "persist" (0/1, default 0: run the step launches of a full tape's forward
+ * and of its reverse pass each as one cooperative persistent launch, the
+ * workgroups looping over each step's workgroups and meeting at a grid-wide
+ * barrier between steps; same work and arithmetic as the launch per step;
+ * checkpointed tapes keep one launch per step; graphs are not used);
  * "graph" (0/1, default 1:
  * capture each tape forward/backward launch sequence once in a HIP graph on
  * an internal stream and replay it on the caller's stream; the cache is keyed
@@ -196,6 +209,14 @@ mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value);
 #define MPM_KERNEL_FWD 0
 #define MPM_KERNEL_BWD 1
 mpm_status mpm_kernel_stats(mpm_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);
+
+/* Scatter-tile counters (measurement support, not part of the method): with
+ * the knob "tile_stats" on, every workgroup's scatter (the forward's p2g, the
+ * reverse pass's g2p* and p2g recompute) counts whether it accumulated in an
+ * LDS tile or fell back to global atomics (its stencils' box exceeded the
+ * tile, or held particles of another box). Synchronises `stream`, returns the
+ * counts since the previous call and resets them. */
+mpm_status mpm_tile_stats(mpm_ctx* ctx, void* stream, int64_t* lds_scatters, int64_t* fallback_scatters);
 
 /* One forward step, state `in` (step `step`) -> `out` (step + 1), in the
  * caller's particle order: clear_grid, compute_actuation (row `step` of
@@ -242,13 +263,16 @@ mpm_status mpm_step_bwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, co
  * checkpoint during the reverse pass (Appendix D.2). Host-only. */
 mpm_status mpm_tape_create(mpm_ctx* ctx, int32_t n_steps, int32_t ckpt_every, mpm_tape** out);
 
-/* Bytes of device memory the tape needs (state slots + FP64 accumulators). */
+/* Bytes of device memory the tape needs (state slots + FP64 accumulators):
+ * T + 1 states for a full tape, or the checkpoints of Appendix D.2 plus the
+ * ring of recomputed states. Support call. */
 size_t mpm_tape_bytes(const mpm_tape* tape);
 
-/* Binds caller-owned tape memory (>= mpm_tape_bytes, 256-byte aligned). */
+/* Binds caller-owned tape memory (>= mpm_tape_bytes, 256-byte aligned).
+ * Support call. */
 mpm_status mpm_tape_bind(mpm_tape* tape, void* dev, size_t bytes);
 
-/* Destroys the tape's host objects. */
+/* Destroys the tape's host objects. Support call. */
 void mpm_tape_destroy(mpm_tape* tape);
 
 /* Runs n_steps forward steps from `init` (caller order) and writes the final
@@ -286,7 +310,9 @@ mpm_status mpm_sort_order(mpm_ctx* ctx, const mpm_state* state, int32_t* perm, v
  * Writes loss_dev[n_scenes] (device, overwritten) and, if seed is non-null,
  * OVERWRITES every component of *seed with dL/d(final state), where
  * L = sum_k L_k (so x-seed = sign / N_k on `axis`, zero elsewhere). With
- * uniform particle mass per scene this is also the centre-of-mass loss. */
+ * uniform particle mass per scene this is also the centre-of-mass loss, so no
+ * separate mass-weighted kind exists: particle mass is per scene (rho * vol of
+ * mpm_params), and a mass-weighted mean equals the plain one. */
 #define MPM_LOSS_MEAN_POS 0
 mpm_status mpm_loss(mpm_ctx* ctx, int32_t kind, int32_t axis, float sign, const mpm_state* final_state,
                     float* loss_dev, mpm_state* seed, void* stream);
@@ -302,7 +328,8 @@ mpm_status mpm_actuation(mpm_ctx* ctx, const float* W, const float* b, int32_t n
 mpm_status mpm_actuation_bwd(mpm_ctx* ctx, const float* W, const float* b, int32_t n_sin, float omega,
                              int32_t n_steps, const float* gact, float* gW, float* gb, void* stream);
 
-/* Synchronises `stream`, reads and clears the device error word. *flags gets
+/* Support call (the paper defines no error reporting): synchronises
+ * `stream`, reads and clears the device error word. *flags gets
  * the MPM_FLAG_* bits; the return value maps the lowest set bit to
  * MPM_E_DOMAIN / MPM_E_INVERTED / MPM_E_NONFINITE (MPM_OK if none). */
 mpm_status mpm_check_errors(mpm_ctx* ctx, void* stream, uint32_t* flags);

@@ -99,6 +99,8 @@ _SIGNATURES = {
     "mpm_check_errors": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
     "mpm_kernel_stats": (c_int32, [c_void_p, c_int32, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int64)]),
+    "mpm_tile_stats": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_int64)]),
     # include/smoke.h
     "smoke_tape_bytes": (c_size_t, [ctypes.POINTER(smoke_desc)]),
     "smoke_workspace_bytes": (c_size_t, [ctypes.POINTER(smoke_desc)]),
@@ -234,6 +236,13 @@ def mpm_kernel_stats(ctx, kernel):
     n = ctypes.c_int64(0)
     call("mpm_kernel_stats", ctx, int(kernel), ctypes.byref(ms), ctypes.byref(n))
     return float(ms.value), int(n.value)
+
+
+def mpm_tile_stats(ctx, stream):
+    a = ctypes.c_int64(0)
+    b = ctypes.c_int64(0)
+    call("mpm_tile_stats", ctx, c_void_p(stream), ctypes.byref(a), ctypes.byref(b))
+    return int(a.value), int(b.value)
 
 
 def mpm_check_errors(ctx, stream):

@@ -48,6 +48,7 @@ enum Region {
   R_GE,        // n_scenes double
   R_GACT,      // kMaxAct double (single-step adjoint)
   R_ERR,       // 1 uint32
+  R_TSTATS,    // 2 uint64: scatter tile counters (knob "tile_stats")
   R_BLOCKS,    // int4 per workgroup: the plain table padded (single steps, in the caller's order)
   R_PLAIN,     // int4 per workgroup: the plain partition (runs of consecutive particles)
   R_PART,      // int32 per parent block: workgroups it emits, scanned
@@ -89,6 +90,15 @@ struct mpm_ctx {
   int lanes = 1;
   int graph = 1;
   int part = 1;      // 1: workgroups aligned to the Morton cell hierarchy (rebuilt at each sort)
+  int persist = 0;   // 1: a full tape's step launches run as one cooperative persistent launch
+  int tile_stats = 0;  // 1: count LDS-tile and fallback scatters (R_TSTATS)
+  int presum = 0;    // 1: sort by stencil base; run sums before the LDS scatter atomics
+  // While a persistent sequence is enqueued: step launches are appended here
+  // instead of being launched.
+  std::vector<FwdArgs>* rec_fwd = nullptr;
+  std::vector<BwdArgs>* rec_bwd = nullptr;
+  int persist_grid[2] = {0, 0};  // co-resident workgroups of the persistent kernels (0: not queried)
+  int persist_grid_shape[2] = {0, 0};  // block * 8 + lanes they were queried for
   int model = 0;     // constitutive model: 0 neo-Hookean, 1 fixed-corotated (MPM_MODEL_COROTATED)
   int n_blocks = 0;  // workgroups per particle pass for the current block and lanes
   int n_plain = 0;   // workgroups of the plain partition
@@ -136,13 +146,18 @@ struct mpm_tape {
   int T = 0, K = 0;
   bool full = true;
   int n_ckpt = 0, R = 0, n_slots = 0;
-  size_t slot_floats = 0, off_gact = 0, off_perm = 0, off_act = 0, off_mat = 0, off_blocks = 0, total = 0;
+  size_t slot_floats = 0, off_gact = 0, off_perm = 0, off_act = 0, off_mat = 0, off_blocks = 0, off_seq = 0,
+         total = 0;
+  // Recorded step launches of the persistent form (host copies; uploaded
+  // into the tape's sequence region before each persistent launch).
+  std::vector<FwdArgs> seq_fwd;
+  std::vector<BwdArgs> seq_bwd;
   char* mem = nullptr;
   bool recorded = false;
   mpm_params rec{};
   // Launch shape the recorded forward sorted and partitioned for (knobs
   // "block", "lanes", "part"); the reverse pass needs the same.
-  int rec_block = 0, rec_lanes = 0, rec_part = 0;
+  int rec_block = 0, rec_lanes = 0, rec_part = 0, rec_presum = 0;
   std::vector<int> ring_holds;
   // Captured launch sequences (knob "graph"): key = every pointer and size the
   // sequence depends on plus the checkpoint-ring state it starts from; the
@@ -179,6 +194,7 @@ struct mpm_tape {
   int* act_ids() const { return reinterpret_cast<int*>(mem + off_act); }
   int* mat_ids() const { return reinterpret_cast<int*>(mem + off_mat); }
   int4* blocks() const { return reinterpret_cast<int4*>(mem + off_blocks); }
+  char* seq() const { return mem + off_seq; }
 };
 
 namespace {
@@ -221,8 +237,10 @@ StepConsts consts(const mpm_ctx& c, const mpm_params* p, const mpm_tape* tp, con
   k.kappa = 4.0f / (c.dx * c.dx);
   k.act_strength = c.act_strength;
   k.lds = c.lds;
-  k.remap = c.remap;
-  k.rotate = c.rotate;
+  // Base-sorted run sums need every lane of a run to visit its stencil in
+  // the same order, on consecutive lanes.
+  k.remap = c.presum ? 0 : c.remap;
+  k.rotate = c.presum ? 0 : c.rotate;
   k.blocks = (c.ns > 1 || c.part) ? (tp ? tp->blocks() : table) : nullptr;
   k.n_blocks = c.n_blocks;
   k.E = p->E;
@@ -232,11 +250,14 @@ StepConsts consts(const mpm_ctx& c, const mpm_params* p, const mpm_tape* tp, con
   k.act_id = (c.n_act > 0) ? act_id : nullptr;
   k.mat_id = p->mat_id ? (tp ? tp->mat_ids() : p->mat_id) : nullptr;
   k.err = err;
+  k.tstats = nullptr;
   return k;
 }
 
 StepConsts consts(const mpm_ctx& c, const mpm_params* p, const mpm_tape* tp) {
-  return consts(c, p, tp, c.at<int4>(R_BLOCKS), c.at<unsigned>(R_ERR));
+  StepConsts k = consts(c, p, tp, c.at<int4>(R_BLOCKS), c.at<unsigned>(R_ERR));
+  if (c.tile_stats) k.tstats = c.at<unsigned long long>(R_TSTATS);
+  return k;
 }
 
 // Geometry of the cell hierarchy for the aligned partition (P particles per
@@ -368,31 +389,55 @@ struct SpanGuard {
 
 template <int D, int LPP>
 mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& args, hipStream_t st, bool timed) {
-  if (timed) span_step(c, 0, st);
   FwdArgs a = args;
   a.k.threads = c.block;
   a.k.clear_per_role = c.part ? c.n_plain : c.n_blocks;
   a.k.groups = a.k.clear_per_role;
-  if (c.model == 1)
-    hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 1>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
-  else
-    hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 0>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
+  if (c.rec_fwd) {
+    c.rec_fwd->push_back(a);
+    return MPM_OK;
+  }
+  if (timed) span_step(c, 0, st);
+  const bool pre = LPP == 1 && c.presum;
+  if (c.model == 1) {
+    if (pre)
+      hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 1, LPP == 1>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
+    else
+      hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 1>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
+  } else {
+    if (pre)
+      hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 0, LPP == 1>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
+    else
+      hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 0>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
+  }
   LAUNCH_TRY();
   return MPM_OK;
 }
 
 template <int D, int LPP>
 mpm_status launch_bwd(const mpm_ctx& c, const BwdArgs& args, hipStream_t st) {
-  span_step(c, 1, st);
   const int nb = c.n_blocks * (args.split_c ? 2 : 1);
   BwdArgs a = args;
   a.k.threads = c.block;
   a.k.clear_per_role = c.part ? c.n_plain : c.n_blocks;
   a.k.groups = (args.split_c ? 2 : 1) * a.k.clear_per_role;
-  if (c.model == 1)
-    hipLaunchKernelGGL((mpm::k_bwd<D, LPP, 1>), dim3(nb), dim3(c.block), 0, st, a);
-  else
-    hipLaunchKernelGGL((mpm::k_bwd<D, LPP, 0>), dim3(nb), dim3(c.block), 0, st, a);
+  if (c.rec_bwd) {
+    c.rec_bwd->push_back(a);
+    return MPM_OK;
+  }
+  span_step(c, 1, st);
+  const bool pre = LPP == 1 && c.presum;
+  if (c.model == 1) {
+    if (pre)
+      hipLaunchKernelGGL((mpm::k_bwd<D, LPP, 1, LPP == 1>), dim3(nb), dim3(c.block), 0, st, a);
+    else
+      hipLaunchKernelGGL((mpm::k_bwd<D, LPP, 1>), dim3(nb), dim3(c.block), 0, st, a);
+  } else {
+    if (pre)
+      hipLaunchKernelGGL((mpm::k_bwd<D, LPP, 0, LPP == 1>), dim3(nb), dim3(c.block), 0, st, a);
+    else
+      hipLaunchKernelGGL((mpm::k_bwd<D, LPP, 0>), dim3(nb), dim3(c.block), 0, st, a);
+  }
   LAUNCH_TRY();
   return MPM_OK;
 }
@@ -413,6 +458,90 @@ mpm_status bwd(const mpm_ctx& c, const BwdArgs& a, hipStream_t st) {
   }
   if (c.lanes == 4) return launch_bwd<3, 4>(c, a, st);
   return c.lanes == 2 ? launch_bwd<3, 2>(c, a, st) : launch_bwd<3, 1>(c, a, st);
+}
+
+// Co-resident workgroups of a persistent kernel at the context's block size
+// (queried once per kernel, block size and lanes).
+template <class K>
+mpm_status persist_grid(const mpm_ctx& cc, int kind, K kernel, int* out) {
+  mpm_ctx& c = const_cast<mpm_ctx&>(cc);
+  const int shape = c.block * 8 + c.lanes;
+  if (c.persist_grid[kind] == 0 || c.persist_grid_shape[kind] != shape) {
+    int per_cu = 0, dev = 0, cus = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, c.block, 0));
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (per_cu < 1 || cus < 1) return MPM_E_HIP;
+    c.persist_grid[kind] = per_cu * cus;
+    c.persist_grid_shape[kind] = shape;
+  }
+  *out = c.persist_grid[kind];
+  return MPM_OK;
+}
+
+// One cooperative launch of `kernel` over the `n` recorded launches at
+// `dev_seq` (kind 0 forward, 1 reverse). With the "timing" knob the launch is
+// one timed span of n step launches.
+template <class K>
+mpm_status launch_persist(const mpm_ctx& c, int kind, K kernel, const void* dev_seq, int n, int max_blocks,
+                          hipStream_t st) {
+  if (n <= 0) return MPM_OK;
+  int grid = 0;
+  const mpm_status gs = persist_grid(c, kind, kernel, &grid);
+  if (gs != MPM_OK) return gs;
+  grid = std::min(grid, max_blocks);
+  span_close(c);
+  mpm_ctx& cm = const_cast<mpm_ctx&>(c);
+  hipEvent_t e0 = nullptr;
+  if (c.timing) {
+    e0 = pool_event(cm);
+    if (!e0 || hipEventRecord(e0, st) != hipSuccess) e0 = nullptr;
+  }
+  const void* seq = dev_seq;
+  int nn = n;
+  void* args[] = {&seq, &nn};
+  HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(c.block), args, 0, st));
+  if (e0) {
+    hipEvent_t e1 = pool_event(cm);
+    if (e1 && hipEventRecord(e1, st) == hipSuccess) cm.ev_pending.push_back({kind, e0, e1, long(n)});
+  }
+  return MPM_OK;
+}
+
+mpm_status fwd_persist(const mpm_ctx& c, const void* seq, int n, hipStream_t st) {
+  const int nb = c.n_blocks;
+  if (c.d == 2) {
+    if (c.lanes == 4) return c.model ? launch_persist(c, 0, mpm::k_fwd_persist<2, 4, 1>, seq, n, nb, st)
+                                     : launch_persist(c, 0, mpm::k_fwd_persist<2, 4, 0>, seq, n, nb, st);
+    if (c.lanes == 2) return c.model ? launch_persist(c, 0, mpm::k_fwd_persist<2, 2, 1>, seq, n, nb, st)
+                                     : launch_persist(c, 0, mpm::k_fwd_persist<2, 2, 0>, seq, n, nb, st);
+    return c.model ? launch_persist(c, 0, mpm::k_fwd_persist<2, 1, 1>, seq, n, nb, st)
+                   : launch_persist(c, 0, mpm::k_fwd_persist<2, 1, 0>, seq, n, nb, st);
+  }
+  if (c.lanes == 4) return c.model ? launch_persist(c, 0, mpm::k_fwd_persist<3, 4, 1>, seq, n, nb, st)
+                                   : launch_persist(c, 0, mpm::k_fwd_persist<3, 4, 0>, seq, n, nb, st);
+  if (c.lanes == 2) return c.model ? launch_persist(c, 0, mpm::k_fwd_persist<3, 2, 1>, seq, n, nb, st)
+                                   : launch_persist(c, 0, mpm::k_fwd_persist<3, 2, 0>, seq, n, nb, st);
+  return c.model ? launch_persist(c, 0, mpm::k_fwd_persist<3, 1, 1>, seq, n, nb, st)
+                 : launch_persist(c, 0, mpm::k_fwd_persist<3, 1, 0>, seq, n, nb, st);
+}
+
+mpm_status bwd_persist(const mpm_ctx& c, const void* seq, int n, hipStream_t st) {
+  const int nb = 2 * c.n_blocks;
+  if (c.d == 2) {
+    if (c.lanes == 4) return c.model ? launch_persist(c, 1, mpm::k_bwd_persist<2, 4, 1>, seq, n, nb, st)
+                                     : launch_persist(c, 1, mpm::k_bwd_persist<2, 4, 0>, seq, n, nb, st);
+    if (c.lanes == 2) return c.model ? launch_persist(c, 1, mpm::k_bwd_persist<2, 2, 1>, seq, n, nb, st)
+                                     : launch_persist(c, 1, mpm::k_bwd_persist<2, 2, 0>, seq, n, nb, st);
+    return c.model ? launch_persist(c, 1, mpm::k_bwd_persist<2, 1, 1>, seq, n, nb, st)
+                   : launch_persist(c, 1, mpm::k_bwd_persist<2, 1, 0>, seq, n, nb, st);
+  }
+  if (c.lanes == 4) return c.model ? launch_persist(c, 1, mpm::k_bwd_persist<3, 4, 1>, seq, n, nb, st)
+                                   : launch_persist(c, 1, mpm::k_bwd_persist<3, 4, 0>, seq, n, nb, st);
+  if (c.lanes == 2) return c.model ? launch_persist(c, 1, mpm::k_bwd_persist<3, 2, 1>, seq, n, nb, st)
+                                   : launch_persist(c, 1, mpm::k_bwd_persist<3, 2, 0>, seq, n, nb, st);
+  return c.model ? launch_persist(c, 1, mpm::k_bwd_persist<3, 1, 1>, seq, n, nb, st)
+                 : launch_persist(c, 1, mpm::k_bwd_persist<3, 1, 0>, seq, n, nb, st);
 }
 
 FwdArgs fwd_args(const mpm_ctx& c, const mpm_params* p, const mpm_tape* tp) {
@@ -477,11 +606,11 @@ mpm_status sort_particles(const mpm_ctx& c, StateRef st, int* perm, int4* table,
   const int pb = (c.N + 255) / 256;
   unsigned* keys[2] = {c.at<unsigned>(R_KEYS), c.at<unsigned>(R_KEYS2)};
   if (c.d == 2)
-    hipLaunchKernelGGL(mpm::k_sort_keys<2>, dim3(pb), dim3(256), 0, s, st, c.N, sid, 1.0f / c.dx, c.n, c.bits,
-                       c.cells_per_scene, keys[0], counts);
+    hipLaunchKernelGGL(mpm::k_sort_keys<2>, dim3(pb), dim3(256), 0, s, st, c.N, sid, 1.0f / c.dx,
+                       c.presum ? 0.5f : 0.0f, c.n, c.bits, c.cells_per_scene, keys[0], counts);
   else
-    hipLaunchKernelGGL(mpm::k_sort_keys<3>, dim3(pb), dim3(256), 0, s, st, c.N, sid, 1.0f / c.dx, c.n, c.bits,
-                       c.cells_per_scene, keys[0], counts);
+    hipLaunchKernelGGL(mpm::k_sort_keys<3>, dim3(pb), dim3(256), 0, s, st, c.N, sid, 1.0f / c.dx,
+                       c.presum ? 0.5f : 0.0f, c.n, c.bits, c.cells_per_scene, keys[0], counts);
   LAUNCH_TRY();
   // Cell starts (the partition's input).
   const int nb = int((nk + mpm::kScanChunk - 1) / mpm::kScanChunk);
@@ -659,6 +788,7 @@ struct StepBufs {
   float4* grid;
   const int4* table;
   unsigned* err;
+  unsigned long long* tstats;  // scatter tile counters, or null
 };
 
 // One forward step in the caller's order: clear the grid, p2g, then grid_op
@@ -673,6 +803,7 @@ mpm_status enqueue_step_fwd(const mpm_ctx& c, const mpm_params* params, int step
   FwdArgs a;
   std::memset(&a, 0, sizeof(a));
   a.k = consts(c, params, nullptr, b.table, b.err);
+  a.k.tstats = b.tstats;
   a.in = user_ref(c, in);
   a.grid_out = b.grid;
   a.act_row = act_row(c, params, step);
@@ -776,6 +907,7 @@ mpm_status mpm_init(const mpm_desc* desc, mpm_ctx** out) {
   c->bytes[R_GE] = size_t(c->ns) * sizeof(double);
   c->bytes[R_GACT] = size_t(mpm::kMaxAct) * sizeof(double);
   c->bytes[R_ERR] = sizeof(unsigned);
+  c->bytes[R_TSTATS] = 2 * sizeof(unsigned long long);
   // At least 16 particles per workgroup (64 threads, 4 lanes each); the
   // aligned partition may use up to twice the plain one's workgroups.
   const size_t plain_max = N / 16 + size_t(c->ns) + 1;
@@ -818,6 +950,7 @@ mpm_status mpm_bind_workspace(mpm_ctx* ctx, void* dev, size_t bytes) {
   HIP_TRY(hipMemcpy(ctx->at<int>(R_OFFSETS), ctx->offsets.data(), ctx->offsets.size() * sizeof(int),
                     hipMemcpyHostToDevice));
   HIP_TRY(hipMemset(ctx->at<unsigned>(R_ERR), 0, sizeof(unsigned)));
+  HIP_TRY(hipMemset(ctx->at<unsigned long long>(R_TSTATS), 0, 2 * sizeof(unsigned long long)));
   return update_blocks(*ctx);
 }
 
@@ -859,6 +992,21 @@ mpm_status mpm_set_knob(mpm_ctx* ctx, const char* key, int64_t value) {
     ctx->part = int(value);
     return update_blocks(*ctx);
   }
+  if (k == "presum") {
+    if (value != 0 && value != 1) return MPM_E_ARG;
+    ctx->presum = int(value);
+    return MPM_OK;
+  }
+  if (k == "tile_stats") {
+    if (value != 0 && value != 1) return MPM_E_ARG;
+    ctx->tile_stats = int(value);
+    return MPM_OK;
+  }
+  if (k == "persist") {
+    if (value != 0 && value != 1) return MPM_E_ARG;
+    ctx->persist = int(value);
+    return MPM_OK;
+  }
   if (k == "split") {
     if (value != 0 && value != 1) return MPM_E_ARG;
     ctx->split_c = int(value);
@@ -899,7 +1047,8 @@ mpm_status mpm_step_fwd(mpm_ctx* ctx, const mpm_params* params, int32_t step, co
   const mpm_ctx& c = *ctx;
   const SpanGuard guard(c);
   c.gstate[kGridB] = kDirty;  // written below without a box record
-  const StepBufs b{c.grid(kGridB), c.at<int4>(R_BLOCKS), c.at<unsigned>(R_ERR)};
+  const StepBufs b{c.grid(kGridB), c.at<int4>(R_BLOCKS), c.at<unsigned>(R_ERR),
+                   c.tile_stats ? c.at<unsigned long long>(R_TSTATS) : nullptr};
   return enqueue_step_fwd(c, params, step, in, out, b, true, static_cast<hipStream_t>(stream));
 }
 
@@ -919,7 +1068,7 @@ mpm_status mpm_step_fwd_noalloc(mpm_ctx* ctx, const mpm_params* params, int32_t 
   // context's every call, stream-ordered before the launches that read it.
   if (table_bytes) HIP_TRY(hipMemcpyAsync(table, c.blocks_host.data(), table_bytes, hipMemcpyHostToDevice, s));
   const StepBufs b{reinterpret_cast<float4*>(base), c.blocks_host.empty() ? nullptr : table,
-                   reinterpret_cast<unsigned*>(err_flags)};
+                   reinterpret_cast<unsigned*>(err_flags), nullptr};
   return enqueue_step_fwd(c, params, step, in, out, b, false, s);
 }
 
@@ -1007,7 +1156,10 @@ mpm_status mpm_tape_create(mpm_ctx* ctx, int32_t n_steps, int32_t ckpt_every, mp
   t->off_act = align_up(t->off_perm + N * sizeof(int));
   t->off_mat = align_up(t->off_act + N * sizeof(int));
   t->off_blocks = align_up(t->off_mat + N * sizeof(int));
-  t->total = align_up(t->off_blocks + size_t(ctx->blocks_cap) * sizeof(int4));
+  t->off_seq = align_up(t->off_blocks + size_t(ctx->blocks_cap) * sizeof(int4));
+  // Persistent form (full tapes): the T + 1 reverse or T forward launches.
+  const size_t seq_bytes = t->full ? size_t(n_steps + 1) * std::max(sizeof(FwdArgs), sizeof(BwdArgs)) : 0;
+  t->total = align_up(t->off_seq + seq_bytes);
   *out = t;
   return MPM_OK;
 }
@@ -1053,7 +1205,19 @@ mpm_status enqueue_tape_forward(mpm_tape* tape, const mpm_params* params, const 
                        tape->mat_ids(), perm, c.N);
     LAUNCH_TRY();
   }
-  TRY(run_forward(*tape, params, 0, tape->T, s));
+  if (c.persist && tape->full) {
+    // Record the step launches, upload them, run them in one persistent launch.
+    tape->seq_fwd.clear();
+    c.rec_fwd = &tape->seq_fwd;
+    const mpm_status rs = run_forward(*tape, params, 0, tape->T, s);
+    c.rec_fwd = nullptr;
+    TRY(rs);
+    const size_t bytes = tape->seq_fwd.size() * sizeof(FwdArgs);
+    HIP_TRY(hipMemcpyAsync(tape->seq(), tape->seq_fwd.data(), bytes, hipMemcpyHostToDevice, s));
+    TRY(fwd_persist(c, tape->seq(), int(tape->seq_fwd.size()), s));
+  } else {
+    TRY(run_forward(*tape, params, 0, tape->T, s));
+  }
   TRY(scatter_state(c, tape->slot(tape->T), user_ref(c, final_state), perm, s));
   return MPM_OK;
 }
@@ -1085,6 +1249,16 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
     a.act_row = act_row(c, params, T - 1);
     a.do_p2g = 1;
     TRY(fwd(c, a, s));
+  }
+  const bool persist = c.persist && tape->full;
+  // Recording ends when this function returns, also on an error.
+  struct RecordGuard {
+    mpm_ctx& c;
+    ~RecordGuard() { c.rec_bwd = nullptr; }
+  } record_guard{c};
+  if (persist) {
+    tape->seq_bwd.clear();
+    c.rec_bwd = &tape->seq_bwd;
   }
   for (int st = T - 1; st >= 0; --st) {
     TRY(ensure_state(*tape, params, st, s));
@@ -1139,7 +1313,14 @@ mpm_status enqueue_tape_backward(mpm_tape* tape, const mpm_params* params, const
     b.final_out = 1;
     b.out = user_ref(c, init_grad);
     b.out_perm = perm;
-    TRY(bwd(c, b, s));
+    const mpm_status bs = bwd(c, b, s);
+    c.rec_bwd = nullptr;
+    TRY(bs);
+  }
+  if (persist) {
+    const size_t bytes = tape->seq_bwd.size() * sizeof(BwdArgs);
+    HIP_TRY(hipMemcpyAsync(tape->seq(), tape->seq_bwd.data(), bytes, hipMemcpyHostToDevice, s));
+    TRY(bwd_persist(c, tape->seq(), int(tape->seq_bwd.size()), s));
   }
   span_close(c);
   if (pg && pg->E) {
@@ -1167,7 +1348,7 @@ std::vector<uintptr_t> graph_key(const mpm_tape* tape, int kind, const mpm_param
   const mpm_ctx& c = *tape->ctx;
   std::vector<uintptr_t> k = {uintptr_t(kind), reinterpret_cast<uintptr_t>(c.ws), reinterpret_cast<uintptr_t>(tape->mem),
                               uintptr_t(c.block), uintptr_t(c.lds), uintptr_t(c.split_c), uintptr_t(c.remap), uintptr_t(c.rotate), uintptr_t(c.lanes),
-                              uintptr_t(c.part),
+                              uintptr_t(c.part), uintptr_t(c.presum),
                               reinterpret_cast<uintptr_t>(p->E), reinterpret_cast<uintptr_t>(p->nu),
                               reinterpret_cast<uintptr_t>(p->vol), reinterpret_cast<uintptr_t>(p->rho),
                               reinterpret_cast<uintptr_t>(p->act_id), reinterpret_cast<uintptr_t>(p->act),
@@ -1185,7 +1366,7 @@ std::vector<uintptr_t> graph_key(const mpm_tape* tape, int kind, const mpm_param
 template <class Fn>
 mpm_status run_graphed(mpm_tape* tape, std::vector<uintptr_t> key, hipStream_t s, Fn&& enqueue) {
   mpm_ctx& c = *tape->ctx;
-  if (!c.graph || c.timing) return enqueue(s);
+  if (!c.graph || c.timing || c.persist) return enqueue(s);
   for (auto& g : tape->graphs) {
     if (g.key == key) {
       HIP_TRY(hipGraphLaunch(g.exec, s));
@@ -1237,6 +1418,7 @@ mpm_status mpm_tape_forward(mpm_tape* tape, const mpm_params* params, const mpm_
   tape->rec_block = tape->ctx->block;
   tape->rec_lanes = tape->ctx->lanes;
   tape->rec_part = tape->ctx->part;
+  tape->rec_presum = tape->ctx->presum;
   tape->recorded = true;
   return MPM_OK;
 }
@@ -1246,7 +1428,9 @@ mpm_status mpm_tape_backward(mpm_tape* tape, const mpm_params* params, const mpm
   if (!tape || !params_ok(params) || !state_ok(final_grad) || !state_ok(init_grad)) return MPM_E_ARG;
   if (!tape->mem || !tape->recorded || !same_params(tape->rec, params)) return MPM_E_TAPE;
   const mpm_ctx& cx = *tape->ctx;
-  if (cx.block != tape->rec_block || cx.lanes != tape->rec_lanes || cx.part != tape->rec_part) return MPM_E_TAPE;
+  if (cx.block != tape->rec_block || cx.lanes != tape->rec_lanes || cx.part != tape->rec_part ||
+      cx.presum != tape->rec_presum)
+    return MPM_E_TAPE;
   if (!tape->ctx->ws) return MPM_E_STATE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const SpanGuard guard(*tape->ctx);
@@ -1308,6 +1492,19 @@ mpm_status mpm_actuation_bwd(mpm_ctx* ctx, const float* W, const float* b, int32
   hipLaunchKernelGGL(mpm::k_actuation_bwd, dim3((n + 63) / 64), dim3(64), 0, static_cast<hipStream_t>(stream), W, b,
                      ctx->n_act, n_sin, omega, ctx->dt, n_steps, gact, gW, gb);
   LAUNCH_TRY();
+  return MPM_OK;
+}
+
+mpm_status mpm_tile_stats(mpm_ctx* ctx, void* stream, int64_t* lds_scatters, int64_t* fallback_scatters) {
+  if (!ctx || !lds_scatters || !fallback_scatters) return MPM_E_ARG;
+  if (!ctx->ws) return MPM_E_STATE;
+  HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  unsigned long long v[2] = {0, 0};
+  HIP_TRY(hipMemcpy(v, ctx->at<unsigned long long>(R_TSTATS), sizeof(v), hipMemcpyDeviceToHost));
+  const unsigned long long zero[2] = {0, 0};
+  HIP_TRY(hipMemcpy(ctx->at<unsigned long long>(R_TSTATS), zero, sizeof(zero), hipMemcpyHostToDevice));
+  *lds_scatters = int64_t(v[0]);
+  *fallback_scatters = int64_t(v[1]);
   return MPM_OK;
 }
 

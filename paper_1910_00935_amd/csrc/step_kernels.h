@@ -35,6 +35,8 @@
 // flush converts each node back to float once.
 #pragma once
 
+#include <hip/hip_cooperative_groups.h>
+
 #include <climits>
 
 #include "device_math.h"
@@ -73,6 +75,8 @@ struct StepConsts {
   const float* rho;
   const int* act_id;    // [N] in this launch's particle order, or null
   unsigned* err;
+  unsigned long long* tstats;  // null, or [2]: scatters accumulated in an LDS tile, scatters that fell back
+                               // to global atomics (one count per workgroup and scatter)
 };
 
 struct FwdArgs {
@@ -234,6 +238,21 @@ __device__ __forceinline__ int4 load_uniform(const int4* p) {
   return make_int4(q->x, q->y, q->z, q->w);
 }
 
+// A box record or clear box: a scalar load (load_uniform) when the table was
+// written by an earlier launch; with P (the persistent kernels, where the
+// table was written before the last grid-wide barrier of the same launch) a
+// vector load that bypasses the non-coherent per-CU caches, since the scalar
+// cache is not invalidated by the barrier.
+template <bool P>
+__device__ __forceinline__ int4 load_box(const int4* p) {
+  if constexpr (P) {
+    const volatile int* q = reinterpret_cast<const volatile int*>(p);
+    return make_int4(q[0], q[1], q[2], q[3]);
+  } else {
+    return load_uniform(p);
+  }
+}
+
 // (r / d, r % d) for 0 <= r < 2^16 and 1 <= d <= 2^10, with rcp = (1/d)(1 + 2^-20):
 // the product r * rcp then lies in [r/d, floor(r/d) + 1) exactly as in real
 // arithmetic, so its truncation is the quotient.
@@ -300,14 +319,15 @@ struct ClearJobs {
 
 __device__ __forceinline__ int clear_entries(const ClearSpec& s) { return (s.g && s.box) ? s.nbox : 0; }
 
+template <bool P>
 __device__ __forceinline__ void clear_entry(const ClearSpec& s0, const ClearSpec& s1, int j, int4& lo, int4& ex,
                                             int& which) {
   const int m0 = clear_entries(s0);
   which = j < m0 ? 0 : 1;
   const int4* t = which == 0 ? s0.box : s1.box;
   const int jj = which == 0 ? j : j - m0;
-  lo = load_uniform(t + 2 * jj);
-  ex = load_uniform(t + 2 * jj + 1);
+  lo = load_box<P>(t + 2 * jj);
+  ex = load_box<P>(t + 2 * jj + 1);
 }
 
 // Clear rank of a workgroup: its index among the workgroups that take part in
@@ -319,6 +339,7 @@ __device__ __forceinline__ int clear_rank(const StepConsts& k, int wg, bool seco
   return second_role ? k.clear_per_role + wg : wg;
 }
 
+template <bool P>
 __device__ __forceinline__ ClearJobs clear_jobs_fetch(const ClearSpec& s0, const ClearSpec& s1, int rank, int groups) {
   ClearJobs c;
   c.n = 0;
@@ -328,14 +349,14 @@ __device__ __forceinline__ ClearJobs clear_jobs_fetch(const ClearSpec& s0, const
   for (int r = 0; r < 2; ++r) {
     const int j = rank + r * groups;
     if (j < m) {
-      clear_entry(s0, s1, j, c.lo[r], c.ex[r], c.which[r]);
+      clear_entry<P>(s0, s1, j, c.lo[r], c.ex[r], c.which[r]);
       c.n = r + 1;
     }
   }
   return c;
 }
 
-template <int D>
+template <int D, bool P>
 __device__ __forceinline__ void clear_jobs_run(const ClearJobs& c, const ClearSpec& s0, const ClearSpec& s1,
                                                const StepConsts& k, int rank) {
   if (rank < 0) return;
@@ -347,7 +368,7 @@ __device__ __forceinline__ void clear_jobs_run(const ClearJobs& c, const ClearSp
   for (int j = rank + 2 * k.groups; j < m; j += k.groups) {
     int4 lo, ex;
     int which;
-    clear_entry(s0, s1, j, lo, ex, which);
+    clear_entry<P>(s0, s1, j, lo, ex, which);
     clear_box_nodes<D>(which == 0 ? s0.g : s1.g, lo, ex, k.n, k.nodes, k.n_scenes, k.threads);
   }
   if (s0.g && !s0.box) zero_range(s0.g, s0.dense_n, k.threads, k.groups, rank);
@@ -513,6 +534,76 @@ __device__ __forceinline__ Nodes<D, false> global_nodes(const float4* g, int n) 
   }
   a.n = n;
   return a;
+}
+
+// Lanes of a wave whose particles share a stencil base (particles sorted by
+// base run consecutively) add to the same nodes in the same instruction when
+// every lane visits its stencil in the same order. RunSum sums a value over
+// this lane's run (the adjacent lanes holding its key) within its aligned
+// group of eight lanes (three shifted adds, DPP row_shl by 1, 2, 4; a lane
+// adds the shifted value only when every lane up to the one it comes from
+// holds its key and its group), leaving the run's sum in the run's first lane
+// (head), so one atomic per run replaces one per lane. The order of the
+// additions is fixed, so results do not depend on scheduling.
+template <int K>
+__device__ __forceinline__ float dpp_from_above(float v) {  // lane l gets lane l + K of its row of 16
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + K, 0xF, 0xF, true));
+}
+template <int K>
+__device__ __forceinline__ int dpp_from_above_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x100 + K, 0xF, 0xF, true);
+}
+__device__ __forceinline__ int dpp_from_below_i(int v) {  // lane l gets lane l - 1 of its row of 16
+  return __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);
+}
+
+struct RunSum {
+  bool m1, m2, m4;  // lane + k holds the same key in the same group of eight
+  bool head;
+  __device__ __forceinline__ float operator()(float v) const {
+    // Selects, not products: a lane outside the run may hold anything.
+    const float a1 = dpp_from_above<1>(v);
+    v += m1 ? a1 : 0.0f;
+    const float a2 = dpp_from_above<2>(v);
+    v += m2 ? a2 : 0.0f;
+    const float a4 = dpp_from_above<4>(v);
+    v += m4 ? a4 : 0.0f;
+    return v;
+  }
+};
+
+// Run of this lane: `key` identifies its stencil base (valid lanes only);
+// all lanes of the wave call.
+__device__ __forceinline__ RunSum run_sum(bool valid, int key) {
+  RunSum r;
+  const int lane = int(threadIdx.x & 63);
+  const int kk = valid ? key : -1 - lane;  // an invalid lane forms a run of its own
+  const int g = lane & 7;
+  // Every lane reads its neighbours' keys before any condition: a cross-lane
+  // read from a lane that a branch has switched off returns 0, not its key.
+  const int n1 = dpp_from_above_i<1>(kk);
+  const int n2 = dpp_from_above_i<2>(kk);
+  const int n3 = dpp_from_above_i<3>(kk);
+  const int n4 = dpp_from_above_i<4>(kk);
+  const int p1 = dpp_from_below_i(kk);
+  // A run is contiguous: particles sorted once by base move, so equal keys
+  // need not be adjacent later; lane + k joins only if every lane between
+  // holds the key too.
+  const bool e1 = n1 == kk, e2 = e1 & (n2 == kk), e4 = e2 & (n3 == kk) & (n4 == kk);
+  r.m1 = (g + 1 < 8) & e1;
+  r.m2 = (g + 2 < 8) & e2;
+  r.m4 = (g + 4 < 8) & e4;
+  r.head = (g == 0) | (p1 != kk);
+  return r;
+}
+
+// Linear index of a stencil's base node in its scene's grid (the run key).
+template <int D>
+__device__ __forceinline__ int base_key(const Sten<D>& st, int n) {
+  if constexpr (D == 2)
+    return st.base[0] * n + st.base[1];
+  else
+    return (st.base[0] * n + st.base[1]) * n + st.base[2];
 }
 
 // Scatter target: a box of the scene's grid in LDS, 64-bit fixed point with
@@ -719,12 +810,12 @@ __device__ __forceinline__ Tile<D> block_tile_scaled(bool valid, const int (&bas
 // The box a gather needs, as recorded by the scatter into the same grid one
 // launch earlier (same workgroup, same particle positions). Used only when it
 // lies inside the grid and belongs to this workgroup's scene.
-template <int D>
+template <int D, bool P>
 __device__ __forceinline__ Tile<D> recorded_tile(const int4* table, int wg, int sc, bool one_scene, int enabled,
                                                  int n) {
   Tile<D> T = empty_tile<D>();
   if (!enabled) return T;
-  const int4 l4 = load_uniform(table + 2 * wg), e4 = load_uniform(table + 2 * wg + 1);
+  const int4 l4 = load_box<P>(table + 2 * wg), e4 = load_box<P>(table + 2 * wg + 1);
   const int lo3[3] = {l4.x, l4.y, l4.z}, ex3[3] = {e4.x, e4.y, e4.z};
   int lo[D], ext[D];
   bool inside = true;
@@ -966,17 +1057,31 @@ struct AffineTab {
   }
 };
 
-// p2g: scatter m and P of one particle (A and m v precomputed).
-template <int D, int S0, class SA>
+// p2g: scatter m and P of one particle (A and m v precomputed). With an
+// active RunSum (LDS tiles, base-sorted particles, every lane in the same
+// stencil order), lanes of a run sum their contributions and the run's head
+// adds them.
+template <int D, int S0, bool PRE = false, class SA>
 __device__ __forceinline__ void p2g_body(const StepConsts& k, const Sten<D>& st, float mass, const float (&mv)[D],
-                                         const float (&A)[D][D], const SA& g) {
+                                         const float (&A)[D][D], const SA& g, const RunSum& rs = RunSum{}) {
   const AffineTab<D> mom(st, mv, A);  // m v + A (x_i - x_p)
   for_nodes<D, S0>(st, [&](int o0, int o1, int o2) {
     const float w = wgt<D>(st, o0, o1, o2);
     const int q = g.idx(st, o0, o1, o2);
-    g.add(q, 0, w * mass);
+    if constexpr (PRE) {
+      float val[D + 1];
+      val[0] = rs(w * mass);
 #pragma unroll
-    for (int a = 0; a < D; ++a) g.add(q, 1 + a, w * mom.at(a, o0, o1, o2));
+      for (int a = 0; a < D; ++a) val[1 + a] = rs(w * mom.at(a, o0, o1, o2));
+      if (rs.head) {
+#pragma unroll
+        for (int c = 0; c < D + 1; ++c) g.add(q, c, val[c]);
+      }
+    } else {
+      g.add(q, 0, w * mass);
+#pragma unroll
+      for (int a = 0; a < D; ++a) g.add(q, 1 + a, w * mom.at(a, o0, o1, o2));
+    }
   });
 }
 
@@ -1147,10 +1252,10 @@ __device__ __forceinline__ void g2p_C(const StepConsts& k, const Sten<D>& st, co
 }
 
 // g2p*: scatter v* into the adjoint grid; accumulate x* (px).
-template <int D, int S0, class GA, class SA>
+template <int D, int S0, bool PRE = false, class GA, class SA>
 __device__ __forceinline__ void g2p_adj_body(const StepConsts& k, const Sten<D>& st, const float (&vt)[D],
                                              const float (&Bm)[D][D], const GA& g, const SA& ad, float (&px)[D],
-                                             bool scatter) {
+                                             bool scatter, const RunSum& rs = RunSum{}) {
   float pxa[D] = {};
   const AffineTab<D> rt(st, vt, Bm);  // r = v~ + B (x_i - x_p)
   for_nodes<D, S0>(st, [&](int o0, int o1, int o2) {
@@ -1167,8 +1272,18 @@ __device__ __forceinline__ void g2p_adj_body(const StepConsts& k, const Sten<D>&
     }
     if (scatter) {
       const int q = ad.idx(st, o0, o1, o2);
+      if constexpr (PRE) {
+        float val[D];
 #pragma unroll
-      for (int c = 0; c < D; ++c) ad.add(q, c, w * r[c]);
+        for (int c = 0; c < D; ++c) val[c] = rs(w * r[c]);
+        if (rs.head) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) ad.add(q, c, val[c]);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < D; ++c) ad.add(q, c, w * r[c]);
+      }
     }
 #pragma unroll
     for (int e = 0; e < D; ++e) {
@@ -1195,7 +1310,7 @@ __device__ __forceinline__ int actuator_of(const StepConsts& k, const float* act
 // Scatter of one state into `grid` with an optional LDS tile (all threads
 // call). The fixed-point tile must already be zero over its first D + 1
 // components (zero_tile64).
-template <int D, int LPP, int M>
+template <int D, int LPP, int M, bool PRE = false>
 __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i, int sc, bool one_scene, int sub,
                                           const PState<D>& p, const float* act_row, float4* grid,
                                           long long* tile, BlockRed& rd, unsigned& err, int4* box_out, int wg) {
@@ -1225,11 +1340,19 @@ __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i,
     mass = sp.mass;
     bound = p2g_bound<D>(mass, mv, A, k.dx);
   }
-  const Tile<D> T = block_tile_scaled<D>(ok, st.base, bound, one_scene, k.lds, rd);
+  Tile<D> T = block_tile_scaled<D>(ok, st.base, bound, one_scene, k.lds, rd);
   record_box<D>(box_out, wg, T, one_scene ? sc : -1);
+  // Runs of up to eight equal-base lanes add one sum: three more bits of headroom.
+  const bool presum = PRE && LPP == 1 && T.on;
+  if (presum) T.e -= 3;
+  RunSum rs{};
+  if (presum) rs = run_sum(ok, base_key<D>(st, k.n));
+  if (k.tstats && threadIdx.x == 0 && T.n > 0) atomicAdd(k.tstats + (T.on ? 0 : 1), 1ull);
   float4* g = grid + long(sc) * k.nodes;
   if (ok && (LPP != 4 || sub < 3)) {
-    if (T.on)
+    if (PRE && presum)
+      p2g_body<D, S0, true>(k, st, mass, mv, A, fix_nodes<D>(tile, T), rs);
+    else if (T.on)
       p2g_body<D, S0>(k, st, mass, mv, A, fix_nodes<D>(tile, T));
     else
       p2g_body<D, S0>(k, st, mass, mv, A, global_nodes<D>(g, k.n));
@@ -1294,25 +1417,34 @@ struct LaneMap {
   }
 };
 
-// M: constitutive model (0 neo-Hookean, 1 fixed-corotated).
-template <int D, int LPP, int M>
-__global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
+// LDS of the forward step body.
+template <int D>
+struct FwdShared {
+  long long tile64[(D + 1) * kTileCap<D>];  // P2G scatter tile (fixed point)
+  float vtile[D * kTileCap<D>];              // G2P velocity tile
+  int red[64];
+};
+
+// Forward step of workgroup `wgi` of the launch described by `a` (all threads
+// of the workgroup call). M: constitutive model (0 neo-Hookean, 1
+// fixed-corotated).
+template <int D, int LPP, int M, bool P, bool PRE = false>
+__device__ __forceinline__ void fwd_block(const FwdArgs& a, int wgi, FwdShared<D>& sh) {
   constexpr int S0 = (LPP == 4) ? 1 : (LPP == 2 ? 2 : 3);
-  __shared__ long long tile64[(D + 1) * kTileCap<D>];  // P2G scatter tile (fixed point)
-  __shared__ float vtile[D * kTileCap<D>];              // G2P velocity tile
-  __shared__ int red[64];
+  long long* tile64 = sh.tile64;
+  float* vtile = sh.vtile;
   const StepConsts& k = a.k;
-  BlockRed rd{red, 0, (k.threads + 63) >> 6};
-  const LaneMap<LPP> lm(k, int(blockIdx.x));
+  BlockRed rd{sh.red, 0, (k.threads + 63) >> 6};
+  const LaneMap<LPP> lm(k, wgi);
   const int i = lm.i, sub = lm.sub;
   const bool live = lm.live;
   // Every workgroup holds particles of one scene (scene-aligned workgroups).
   const int sc = lm.scene;
   const bool one_scene = true;
   unsigned err = 0;
-  const int rank = clear_rank(k, int(blockIdx.x), false);
+  const int rank = clear_rank(k, wgi, false);
   if (k.blocks && lm.count == 0 && rank < 0) {  // an unused entry of the aligned partition
-    if (a.do_p2g) record_box<D>(a.box_out, int(blockIdx.x), empty_tile<D>(), -1);
+    if (a.do_p2g) record_box<D>(a.box_out, wgi, empty_tile<D>(), -1);
     return;
   }
   // Every independent global read is issued first: the state, the clear
@@ -1322,12 +1454,12 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   PState<D> p;
   if (live) load_state<D>(a.in, i, p);
   const ClearSpec c0{a.clear, a.clear_box, a.clear_nbox, a.clear_n}, c1{nullptr, nullptr, 0, 0};
-  const ClearJobs cj = clear_jobs_fetch(c0, c1, rank, k.groups);
+  const ClearJobs cj = clear_jobs_fetch<P>(c0, c1, rank, k.groups);
   if (a.do_p2g && k.lds) zero_tile64<D, D + 1>(tile64, k.threads);
   Tile<D> T = empty_tile<D>();
   const float4* g = a.grid_in + long(sc) * k.nodes;
   if (a.do_g2p && a.box_in) {
-    T = recorded_tile<D>(a.box_in, int(blockIdx.x), sc, one_scene, k.lds, k.n);
+    T = recorded_tile<D, P>(a.box_in, wgi, sc, one_scene, k.lds, k.n);
     if (T.on) tile_load_vel<D>(k, T, g, vtile);
   }
   if (a.do_g2p) {
@@ -1339,7 +1471,7 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
       if (T.on) tile_load_vel<D>(k, T, g, vtile);
     }
     if (T.on) __syncthreads();
-    clear_jobs_run<D>(cj, c0, c1, k, rank);
+    clear_jobs_run<D, P>(cj, c0, c1, k, rank);
     if (ok) {
       if (T.on && in_tile<D>(T, st.base))
         g2p_body<D, true, S0>(k, st, lds_nodes<D>(vtile, T), p);
@@ -1350,12 +1482,19 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
     }
     if (live && lm.owner) store_state<D>(a.out, i, p);
   } else {
-    clear_jobs_run<D>(cj, c0, c1, k, rank);
+    clear_jobs_run<D, P>(cj, c0, c1, k, rank);
   }
   if (a.do_p2g)
-    p2g_phase<D, LPP, M>(k, live, i, sc, one_scene, sub, p, a.act_row, a.grid_out, tile64, rd, err, a.box_out,
-                      int(blockIdx.x));
+    p2g_phase<D, LPP, M, PRE>(k, live, i, sc, one_scene, sub, p, a.act_row, a.grid_out, tile64, rd, err, a.box_out, wgi);
   if (err) atomicOr(k.err, err);
+}
+
+// PRE: particles sorted by stencil base, LDS scatters summed over runs of
+// equal-base lanes first (knob "presum"; one lane per particle only).
+template <int D, int LPP, int M, bool PRE = false>
+__global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
+  __shared__ FwdShared<D> sh;
+  fwd_block<D, LPP, M, false, PRE>(a, int(blockIdx.x), sh);
 }
 
 // Sum `val` over the live lanes of the wavefront that share `key`, and add
@@ -1373,20 +1512,30 @@ __device__ __forceinline__ void wave_add_keyed(bool live, int key, double val, d
   }
 }
 
-template <int D, int LPP, int M>
-__global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
+// LDS of the reverse step body.
+template <int D>
+struct BwdShared {
+  float tA[(D + 1) * kTileCap<D>];      // phase A: adjoint tile (P*, m*)
+  float tV[D * kTileCap<D>];            // phase B: velocity tile
+  long long tS[(D + 1) * kTileCap<D>];  // scatter tile: phase B (adjoint grid), phase C (grid)
+  int red[64];
+};
+
+// Reverse step of workgroup `wgi` of the launch described by `a` (all
+// threads of the workgroup call).
+template <int D, int LPP, int M, bool P, bool PRE = false>
+__device__ __forceinline__ void bwd_block(const BwdArgs& a, int wgi, BwdShared<D>& sh) {
   constexpr int S0 = (LPP == 4) ? 1 : (LPP == 2 ? 2 : 3);
-  __shared__ float tA[(D + 1) * kTileCap<D>];      // phase A: adjoint tile (P*, m*)
-  __shared__ float tV[D * kTileCap<D>];            // phase B: velocity tile
-  __shared__ long long tS[(D + 1) * kTileCap<D>];  // scatter tile: phase B (adjoint grid), phase C (grid)
-  __shared__ int red[64];
+  float* tA = sh.tA;
+  float* tV = sh.tV;
+  long long* tS = sh.tS;
   const StepConsts& k = a.k;
-  BlockRed rd{red, 0, (k.threads + 63) >> 6};
+  BlockRed rd{sh.red, 0, (k.threads + 63) >> 6};
   // With split_c, workgroups [0, nb) run phases A and B and workgroups
   // [nb, 2 nb) run phase C on the same particles: C does not depend on A or B.
   const int nb = k.n_blocks;
-  const bool role_c = a.split_c && int(blockIdx.x) >= nb;
-  const int wg = role_c ? int(blockIdx.x) - nb : int(blockIdx.x);
+  const bool role_c = a.split_c && wgi >= nb;
+  const int wg = role_c ? wgi - nb : wgi;
   const LaneMap<LPP> lm(k, wg);
   const int i = lm.i, sub = lm.sub;
   const bool live = lm.live, owner = lm.owner;
@@ -1406,13 +1555,13 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   }
   const ClearSpec c0{a.clear0, a.clear0_box, a.clear0_nbox, a.clear0_n};
   const ClearSpec c1{a.clear1, a.clear1_box, a.clear1_nbox, a.clear1_n};
-  const ClearJobs cj = clear_jobs_fetch(c0, c1, rank, k.groups);
+  const ClearJobs cj = clear_jobs_fetch<P>(c0, c1, rank, k.groups);
   if (role_c) {
     if (k.lds) zero_tile64<D, D + 1>(tS, k.threads);
     PState<D> p;
     if (live) load_state<D>(a.stC, i, p);
-    clear_jobs_run<D>(cj, c0, c1, k, rank);
-    p2g_phase<D, LPP, M>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
+    clear_jobs_run<D, P>(cj, c0, c1, k, rank);
+    p2g_phase<D, LPP, M, PRE>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
     if (err) atomicOr(k.err, err);
     return;
   }
@@ -1460,8 +1609,8 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   }
   if (!a.final_out && k.lds) zero_tile64<D, D>(tS, k.threads);
   Tile<D> TA = empty_tile<D>(), TB = empty_tile<D>();
-  if (a.a_mode == 1 && a.boxA_in) TA = recorded_tile<D>(a.boxA_in, wg, sc, one_scene, k.lds, k.n);
-  if (!a.final_out && a.boxB_in) TB = recorded_tile<D>(a.boxB_in, wg, sc, one_scene, k.lds, k.n);
+  if (a.a_mode == 1 && a.boxA_in) TA = recorded_tile<D, P>(a.boxA_in, wg, sc, one_scene, k.lds, k.n);
+  if (!a.final_out && a.boxB_in) TB = recorded_tile<D, P>(a.boxB_in, wg, sc, one_scene, k.lds, k.n);
   if (TA.on) tile_load_adj<D>(k, TA, a.gA + long(sc) * k.nodes, a.aA + long(sc) * k.nodes, tA);
   if (TB.on) tile_load_vel<D>(k, TB, a.gB + long(sc) * k.nodes, tV);
 
@@ -1550,7 +1699,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   }
 
   if (a.final_out) {
-    clear_jobs_run<D>(cj, c0, c1, k, rank);
+    clear_jobs_run<D, P>(cj, c0, c1, k, rank);
     if (!live || !owner) return;
     const int o = a.out_perm ? a.out_perm[i] : i;
     const int os = a.out.stride;
@@ -1592,7 +1741,7 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
       if (T.on) tile_load_vel<D>(k, T, g, tV);
     }
     if (T.on) __syncthreads();
-    clear_jobs_run<D>(cj, c0, c1, k, rank);
+    clear_jobs_run<D, P>(cj, c0, c1, k, rank);
     const bool in_t = T.on && ok && in_tile<D>(T, st.base);
     float Bm[D][D] = {}, vt[D] = {}, bound = 0.0f;
     if (ok) {
@@ -1648,12 +1797,21 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     }
     record_box_union<D>(a.boxB, wg, T, outside, one_scene ? sc : -1);
     const bool fix = T.on && e_fix != INT_MIN;
+    const bool presum = PRE && LPP == 1 && fix;
+    if (presum) e_fix -= 3;  // runs of up to eight lanes add one sum
+    RunSum rs{};
+    if (presum) rs = run_sum(ok && in_t, base_key<D>(st, k.n));
+    const bool any = T.n > 0 || outside.mn[0] <= outside.mx[0];
+    if (k.tstats && threadIdx.x == 0 && any) atomicAdd(k.tstats + ((fix && outside.mn[0] > outside.mx[0]) ? 0 : 1), 1ull);
     if (ok) {
       const bool scatter = LPP != 4 || sub < 3;
       if (in_t && fix) {
         FixNodes<D> fn = fix_nodes<D>(tS, T);
         fn.e = e_fix;
-        g2p_adj_body<D, S0>(k, st, vt, Bm, lds_nodes<D>(tV, T), fn, px, scatter);
+        if (PRE && presum)
+          g2p_adj_body<D, S0, true>(k, st, vt, Bm, lds_nodes<D>(tV, T), fn, px, scatter, rs);
+        else
+          g2p_adj_body<D, S0>(k, st, vt, Bm, lds_nodes<D>(tV, T), fn, px, scatter);
       } else if (in_t) {
         g2p_adj_body<D, S0>(k, st, vt, Bm, lds_nodes<D>(tV, T), global_nodes<D>(ad, k.n), px, scatter);
       } else {
@@ -1682,9 +1840,50 @@ __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
     if (live) load_state<D>(a.stC, i, p);
     __syncthreads();  // every thread is done with the scatter tile of phase B
     if (k.lds) zero_tile64<D, D + 1>(tS, k.threads);
-    p2g_phase<D, LPP, M>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
+    p2g_phase<D, LPP, M, PRE>(k, live, i, sc, one_scene, sub, p, a.act_rowC, a.gC, tS, rd, err, a.boxC, wg);
   }
   if (err) atomicOr(k.err, err);
+}
+
+template <int D, int LPP, int M, bool PRE = false>
+__global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
+  __shared__ BwdShared<D> sh;
+  bwd_block<D, LPP, M, false, PRE>(a, int(blockIdx.x), sh);
+}
+
+// Persistent forms (knob "persist"): the step launches of a recorded tape
+// sequence run in one cooperative launch; each workgroup loops over the
+// workgroups of each recorded launch (round robin) and all meet at a
+// grid-wide barrier between launches, so the work and arithmetic are those
+// of the launch-per-step form and only the launch boundaries differ.
+template <int D, int LPP, int M>
+__global__ void __launch_bounds__(256) k_fwd_persist(const FwdArgs* __restrict__ seq, int n) {
+  __shared__ FwdShared<D> sh;
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int l = 0; l < n; ++l) {
+    const FwdArgs& a = seq[l];
+    const int nvb = a.k.n_blocks;
+    for (int vb = int(blockIdx.x); vb < nvb; vb += int(gridDim.x)) {
+      fwd_block<D, LPP, M, true>(a, vb, sh);
+      __syncthreads();
+    }
+    grid.sync();
+  }
+}
+
+template <int D, int LPP, int M>
+__global__ void __launch_bounds__(256) k_bwd_persist(const BwdArgs* __restrict__ seq, int n) {
+  __shared__ BwdShared<D> sh;
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int l = 0; l < n; ++l) {
+    const BwdArgs& a = seq[l];
+    const int nvb = a.k.n_blocks * (a.split_c ? 2 : 1);
+    for (int vb = int(blockIdx.x); vb < nvb; vb += int(gridDim.x)) {
+      bwd_block<D, LPP, M, true>(a, vb, sh);
+      __syncthreads();
+    }
+    grid.sync();
+  }
 }
 
 }  // namespace mpm

@@ -33,16 +33,18 @@ __device__ __forceinline__ unsigned morton(const int (&c)[D], int bits) {
   return key;
 }
 
-// key[i] = scene * cells_per_scene + morton(cell of x_i), cells clamped into the grid.
+// key[i] = scene * cells_per_scene + morton(cell of x_i), cells clamped into
+// the grid; the cell of coordinate g is floor(x / dx - shift) (shift 0: the
+// cell holding the particle; 1/2: its stencil base).
 template <int D>
-__global__ void k_sort_keys(StateRef st, int N, const int* scene_id, float inv_dx, int n, int bits,
+__global__ void k_sort_keys(StateRef st, int N, const int* scene_id, float inv_dx, float shift, int n, int bits,
                             unsigned cells_per_scene, unsigned* keys, int* counts) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   int c[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    float g = st.x[a * st.stride + i] * inv_dx;
+    float g = st.x[a * st.stride + i] * inv_dx - shift;
     int ci = (g >= 0.0f) ? (g < float(n - 1) ? int(g) : n - 1) : 0;  // NaN -> 0
     c[a] = ci;
   }

@@ -184,6 +184,10 @@ class Simulator:
         L.mpm_actuation_bwd(self.ctx, W.data_ptr(), b.data_ptr(), W.shape[1], omega, n_steps, gact.data_ptr(),
                             gW.data_ptr(), gb.data_ptr(), _stream())
 
+    def tile_stats(self):
+        """(LDS-tile scatters, fallback scatters) since the last call (knob "tile_stats")."""
+        return L.mpm_tile_stats(self.ctx, _stream())
+
     def check_errors(self):
         """Synchronises and returns the device error flags (MPM_FLAG_* bits)."""
         st, flags = L.mpm_check_errors(self.ctx, _stream())

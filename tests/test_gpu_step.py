@@ -103,3 +103,71 @@ def test_step_bwd_accumulates():
     b = two.to_particle_major()
     for k in range(4):
         np.testing.assert_allclose(b[k], 2 * a[k], rtol=1e-4, atol=1e-6 * np.abs(a[k]).max())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fixed_point_scale_with_one_large_contribution(dim):
+    """A workgroup whose scatter contributions span four orders of magnitude:
+    one particle 1e4 times faster than its neighbours (forward: |m v|; reverse:
+    its seed dL/dv'), so the workgroup's fixed-point scale follows the large
+    bound B. The other particles' contributions are then rounded to B 2^-31;
+    their results must stay within the bound that implies (a node sum of n
+    contributions is off by at most n B 2^-31) and match the oracle."""
+    base = scenes.deform2d() if dim == 2 else scenes.elastic3d()
+    n_keep = 1024 if dim == 2 else 4096
+    from dataclasses import replace
+    rng = np.random.default_rng(20 + dim)
+    # The first lattice points: single steps run in the caller's order, and
+    # 128 consecutive lattice points (four lattice rows) stage a box that
+    # fits the LDS tile.
+    sc = replace(base, offsets=np.array([0, n_keep], np.int32), x=base.x[:n_keep], v=base.v[:n_keep],
+                 C=base.C[:n_keep], F=base.F[:n_keep])
+    small = 1e-2
+    v = (small * rng.normal(size=(n_keep, dim))).astype(np.float32)
+    sim = rt.Simulator.for_scene(sc, knobs={"block": 128, "lanes": 1, "part": 0, "tile_stats": 1})
+    big = 64  # in the first workgroup, particles 0..127
+    wg0 = np.arange(128)
+    v[big] = 100.0 * np.sign(rng.normal(size=dim))
+    sc = replace(sc, v=v)
+    p = rt.params_for_scene(sc)
+    s_in = rt.state_for_scene(sc)
+    s_out = rt.State.empty(dim, n_keep)
+    sim.tile_stats()
+    sim.step_fwd(p, 0, s_in, s_out)
+    assert sim.check_errors() == 0
+    lds, fallback = sim.tile_stats()
+    assert lds > 0 and fallback == 0, (lds, fallback)  # the fixed-point LDS path ran
+    got = s_out.to_particle_major()
+    ref, err = orc.step_fwd(sc, orc.pack(sc.x, sc.v, sc.C, sc.F))
+    assert err == 0
+    ref = orc.unpack(ref, dim)
+    # Particles of the first workgroup more than two cells from the fast one:
+    # their nodes receive none of its contributions, only the coarse rounding.
+    far = wg0[np.linalg.norm(sc.x[wg0] - sc.x[big], axis=1) > 3 * sc.dx]
+    assert len(far) > 32
+    m = float(sc.rho[0] * sc.vol[0])
+    B = m * 100.0 * np.sqrt(dim)  # bound of the fast particle's |m v| contributions
+    per_node = 4.0 ** dim * B * 2.0 ** -30 / (0.5 * m)  # n contributions over a node mass >= m/2 (generous)
+    dv = np.abs(got[1][far] - ref[1][far]).max()
+    log(f"[fixed-point scale {dim}D] forward: max |dv'| of {len(far)} far particles {dv:.3g} "
+        f"(bound {per_node:.3g}; their |v| ~ {small})")
+    assert dv <= per_node, (dv, per_node)
+    assert rel(got[1][far], ref[1][far]) < 1e-2
+    # Reverse: the fast particle's seed dL/dv' is 1e4 times the others'.
+    S = 2 * dim + 2 * dim * dim
+    gout = small * rng.normal(size=(n_keep, S))
+    gout[big, dim:2 * dim] = 100.0
+    gx, gv, gC, gF = orc.unpack(gout, dim)
+    og = rt.State.from_particle_major(gx, gv, gC, gF)
+    ig = rt.State.zeros(dim, n_keep)
+    sim.step_bwd(p, 0, s_in, og, ig)
+    assert sim.check_errors() == 0
+    gout32 = orc.pack(*[a.astype(np.float32) for a in (gx, gv, gC, gF)])
+    rg, _, _, err = orc.step_bwd(sc, orc.pack(sc.x, sc.v, sc.C, sc.F), gout32)
+    assert err == 0
+    rg = orc.unpack(rg, dim)
+    gg = ig.to_particle_major()
+    r = {name: rel(gg[k][far], rg[k][far]) for k, name in enumerate("xvCF")}
+    log(f"[fixed-point scale {dim}D] reverse: far particles' gradients rel {r}")
+    for name, e in r.items():
+        assert e < 1e-3, (name, e)
