@@ -33,6 +33,9 @@ sys.path.insert(0, ROOT)
 METRIC = "fwd+bwd particle-steps/s, 3D MLS-MPM 64³ grid; batched vs per-scene launches"
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_elastic3d.json")
+# Launch configurations chosen by the autotuner on MI355X (paper_1910_00935_amd/autotune.py),
+# keyed by workload shape and GPU architecture.
+TUNED = os.path.join(ROOT, "paper_1910_00935_amd", "tuned.json")
 
 
 def _source_hash():
@@ -176,41 +179,57 @@ def copy_ceiling(torch, nbytes, launches=200):
 
 
 def calibration_copy(torch):
-    """One plain device-to-device copy of COPY_MIB MiB, whose counters give the
-    scale from FETCH_SIZE / WRITE_SIZE readings to bytes."""
-    src = torch.ones(COPY_MIB * 1024 * 1024 // 4, device="cuda")
+    """Kernels of known HBM traffic whose counters give the scale from
+    FETCH_SIZE / WRITE_SIZE readings to bytes: a device-to-device copy of
+    COPY_MIB MiB (reads and writes COPY_MIB MiB), a fill (writes COPY_MIB MiB)
+    and a sum (reads COPY_MIB MiB), each on buffers larger than the caches
+    hold after the others ran."""
+    n = COPY_MIB * 1024 * 1024 // 4
+    src = torch.ones(n, device="cuda")
     dst = torch.empty_like(src)
+    other = torch.empty_like(src)
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
+    other.fill_(2.0)
+    torch.cuda.synchronize()
+    s = dst.sum()
+    torch.cuda.synchronize()
+    return float(s)
+
+
+CALIBRATION = {"copy": "copyBuffer", "fill": "Fill", "sum": "reduce"}
 
 
 def _pmc_means(csv_path, counter):
     """Mean value of `counter` per dispatch for each kernel (short name), and
-    the largest single reading of the copy kernel."""
+    the largest single reading of each calibration kernel (copy, fill, sum;
+    matched by name)."""
     import csv
-    sums, counts, copy_max = {}, {}, 0.0
+    sums, counts, cal = {}, {}, {k: 0.0 for k in CALIBRATION}
     with open(csv_path) as fh:
         for r in csv.DictReader(fh):
             if r["Counter_Name"] != counter:
                 continue
             v = float(r["Counter_Value"])
             name = r["Kernel_Name"]
-            if "copyBuffer" in name:
-                copy_max = max(copy_max, v)
+            for k, pat in CALIBRATION.items():
+                if pat in name:
+                    cal[k] = max(cal[k], v)
             short = name.split("(")[0].split("::")[-1].split("<")[0]
             sums[short] = sums.get(short, 0.0) + v
             counts[short] = counts.get(short, 0) + 1
-    return {k: sums[k] / counts[k] for k in sums}, counts, copy_max
+    return {k: sums[k] / counts[k] for k in sums}, counts, cal
 
 
 def summarize_pmc(fetch_csv, write_csv, knobs, command):
     """profiles/traffic_elastic3d.json from a FETCH_SIZE run and a WRITE_SIZE run of
     `bench.py --profile`: per-dispatch KiB of the step kernels, each scaled by
     the ratio of the calibration copy's known size to its own reading."""
-    fetch, n_f, copy_f = _pmc_means(fetch_csv, "FETCH_SIZE")
-    write, n_w, copy_w = _pmc_means(write_csv, "WRITE_SIZE")
+    fetch, n_f, cal_f = _pmc_means(fetch_csv, "FETCH_SIZE")
+    write, n_w, cal_w = _pmc_means(write_csv, "WRITE_SIZE")
     known_kib = COPY_MIB * 1024.0
+    copy_f, copy_w = cal_f["copy"], cal_w["copy"]
     sf = known_kib / copy_f if copy_f > 0 else None
     sw = known_kib / copy_w if copy_w > 0 else None
     kernels = {}
@@ -222,7 +241,11 @@ def summarize_pmc(fetch_csv, write_csv, knobs, command):
                           "read_bytes": round(rd), "write_bytes": round(wr), "bytes_per_launch": round(rd + wr)}
     rec = {"source_hash": _source_hash(), "knobs": knobs, "command": command,
            "calibration": {"copy_mib": COPY_MIB, "fetch_kib_raw": copy_f, "write_kib_raw": copy_w,
-                           "fetch_scale": sf, "write_scale": sw},
+                           "fetch_scale": sf, "write_scale": sw,
+                           # Cross-check: the read-only sum and the write-only fill of the same size.
+                           "sum_fetch_kib_raw": cal_f["sum"], "fill_write_kib_raw": cal_w["fill"],
+                           "sum_fetch_scale": known_kib / cal_f["sum"] if cal_f["sum"] > 0 else None,
+                           "fill_write_scale": known_kib / cal_w["fill"] if cal_w["fill"] > 0 else None},
            "kernels": kernels}
     with open(PROFILE_TRAFFIC, "w") as fh:
         json.dump(rec, fh, indent=1)
@@ -288,9 +311,30 @@ def run_cpu_baseline_batched(sample_steps, workers):
                       f"{sc.steps} steps, fwd + reverse, one oracle call per scene on {workers} threads, {dt:.1f} s"}
 
 
-def run_batched(args, torch, rt, scenes, n_scenes=256, steps=256):
+def _median_ms(torch, run, repeats):
+    """Median over `repeats` timed calls of run() (after one warmup), each
+    bracketed by events on the current stream."""
+    import statistics
+    run()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ts = []
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return statistics.median(ts), ts
+
+
+def run_batched(args, torch, rt, scenes, n_scenes=256, steps=256, repeats=5):
     """2D workload of `n_scenes` independent scenes: one context (one launch per
-    step for all scenes) against one context per scene run back to back."""
+    step for all scenes), the same with the persistent form (one cooperative
+    launch per direction), and one context per scene run back to back.
+    Medians of `repeats` trajectories each."""
     sc = scenes.batched2d(n_scenes=n_scenes, steps=steps)
     N = sc.n_particles
     knobs = tuned_knobs(sc, args)
@@ -316,27 +360,164 @@ def run_batched(args, torch, rt, scenes, n_scenes=256, steps=256):
         return run, sim
 
     run, sim = make(sc, knobs)
-    run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run()
-    torch.cuda.synchronize()
-    t_batched = time.perf_counter() - t0
+    b_ms, b_all = _median_ms(torch, run, repeats)
+    run_p, sim_p = make(sc, {**knobs, "persist": 1})
+    p_ms, p_all = _median_ms(torch, run_p, repeats)
+    if sim.check_errors() or sim_p.check_errors():
+        raise RuntimeError("batched: simulation error flags set")
     per = [make(sc.subset([k]), knobs_one) for k in range(n_scenes)]
-    for r, _ in per:
-        r()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for r, _ in per:
-        r()
-    torch.cuda.synchronize()
-    t_per = time.perf_counter() - t0
+
+    def run_all():
+        for r, _ in per:
+            r()
+    s_ms, s_all = _median_ms(torch, run_all, max(1, repeats // 2))
+    # Algorithmic bytes: 5 S per particle-step (S = 48 B in 2D); the grids
+    # stay in L2 and are not counted.
+    alg = 5 * 48 * N * steps
     return {"workload": f"2D, {n_scenes} scenes x 64^2 grids, {N} particles (log-uniform 500..8000 per scene), "
                         f"{steps} steps, fwd+bwd",
-            "batched_particle_steps_per_s": N * steps / t_batched,
-            "per_scene_particle_steps_per_s": N * steps / t_per,
-            "speedup": t_per / t_batched, "batched_ms": t_batched * 1e3, "per_scene_ms": t_per * 1e3,
+            "batched_particle_steps_per_s": N * steps / (b_ms * 1e-3),
+            "persistent_particle_steps_per_s": N * steps / (p_ms * 1e-3),
+            "per_scene_particle_steps_per_s": N * steps / (s_ms * 1e-3),
+            "speedup": s_ms / b_ms, "batched_ms": round(b_ms, 3), "persistent_ms": round(p_ms, 3),
+            "per_scene_ms": round(s_ms, 3),
+            "runs_ms": {"batched": [round(t, 3) for t in b_all], "persistent": [round(t, 3) for t in p_all],
+                        "per_scene": [round(t, 3) for t in s_all]},
+            "hbm_frac": round(alg / (b_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "hbm_frac_persistent": round(alg / (p_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "alg_bytes_per_trajectory": alg,
             "knobs_batched": knobs, "knobs_per_scene": knobs_one}
+
+
+def run_elastic3d_long(args, torch, rt, scenes, repeats=3):
+    """The long 3D workload (128^3 grid, 262144 particles, 1024 steps, tape
+    checkpointed every 64 steps, so the reverse pass recomputes each segment
+    from its checkpoint): median trajectory time and HBM fraction against
+    672 B per particle-step (5 S for the step and its adjoint plus 2 S for the
+    segment recompute, S = 96 B)."""
+    sc = scenes.elastic3d_long()
+    T, N, K = sc.steps, sc.n_particles, sc.ckpt_every
+    knobs = tuned_knobs(sc, args)
+    sim = rt.Simulator.for_scene(sc, knobs=knobs)
+    params = rt.params_for_scene(sc)
+    init = rt.state_for_scene(sc)
+    tape = sim.tape(T, K)
+    final, seed, grad = rt.State.empty(3, N), rt.State.empty(3, N), rt.State.zeros(3, N)
+    gE = torch.zeros(1, device="cuda")
+
+    def run():
+        tape.forward(params, init, final)
+        sim.loss_mean(final, sc.loss_axis, sc.loss_sign, seed)
+        tape.backward(params, seed, grad, gE)
+
+    ms, all_ms = _median_ms(torch, run, repeats)
+    if sim.check_errors():
+        raise RuntimeError("elastic3d_long: simulation error flags set")
+    alg = 672 * N * T
+    fb = tile_fallback(torch, rt, sc, knobs)
+    return {"workload": f"3D, 128^3 grid, {N} particles (64^3 lattice), {T} steps, checkpoints every {K}, fwd+bwd "
+                        "with segment recompute",
+            "tile_fallback": fb,
+            "particle_steps_per_s": N * T / (ms * 1e-3), "ms_per_trajectory": round(ms, 3),
+            "runs_ms": [round(t, 3) for t in all_ms], "alg_bytes_per_particle_step": 672,
+            "hbm_frac": round(alg / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4), "knobs": knobs,
+            "tape_bytes": tape.nbytes}
+
+
+def _oracle_rate(sc, steps, act=None):
+    """The FP64 oracle's fwd + reverse particle-steps/s on the first `steps`
+    steps of a scene (one core) and the seconds it took."""
+    import oracle as orc
+    st = orc.pack(sc.x, sc.v, sc.C, sc.F)
+    t0 = time.perf_counter()
+    sT, _, _ = orc.run_fwd(sc, steps, st, act=act)
+    _, seed = orc.loss_mean_pos(sc, sT, sc.loss_axis, sc.loss_sign)
+    orc.run_bwd(sc, steps, steps, st, seed, act=act)
+    dt = time.perf_counter() - t0
+    return sc.n_particles * steps / dt, dt
+
+
+def run_configs(args, torch, rt, scenes, repeats=5):
+    """The small 2D workloads' GPU throughput (median trajectory: tape
+    forward, loss and seed, reverse pass; the actuated body also its
+    actuation signal and adjoint) and the oracle's one-core rate on each,
+    and the oracle's rate on a bounded sample of the long 3D workload."""
+    import oracle as orc
+    out = {}
+    for name in ("translate2d", "deform2d", "actuated2d"):
+        sc = scenes.make(name) if name in scenes.REGISTRY else getattr(scenes, name)()
+        T, N = sc.steps, sc.n_particles
+        knobs = tuned_knobs(sc, args)
+        sim = rt.Simulator.for_scene(sc, knobs=knobs)
+        params = rt.params_for_scene(sc)
+        init = rt.state_for_scene(sc)
+        tape = sim.tape(T, 0)
+        fin, seed, grad = rt.State.empty(2, N), rt.State.empty(2, N), rt.State.zeros(2, N)
+        gE = torch.zeros(1, device="cuda")
+        act_np = None
+        if sc.n_act:
+            W = torch.as_tensor(sc.act_W, device="cuda")
+            b = torch.as_tensor(sc.act_b, device="cuda")
+            gW, gb = torch.zeros_like(W), torch.zeros_like(b)
+            gact = torch.zeros(T, sc.n_act, device="cuda")
+            act_np = orc.actuation(sc.act_W, sc.act_b, sc.act_omega, sc.dt, T)
+
+        def run():
+            if sc.n_act:
+                params.act = sim.actuation(W, b, sc.act_omega, T)
+                tape.forward(params, init, fin)
+                sim.loss_mean(fin, sc.loss_axis, sc.loss_sign, seed)
+                tape.backward(params, seed, grad, gE, gact)
+                sim.actuation_bwd(W, b, sc.act_omega, T, gact, gW, gb)
+            else:
+                tape.forward(params, init, fin)
+                sim.loss_mean(fin, sc.loss_axis, sc.loss_sign, seed)
+                tape.backward(params, seed, grad, gE)
+
+        ms, _ = _median_ms(torch, run, repeats)
+        if sim.check_errors():
+            raise RuntimeError(f"{name}: simulation error flags set")
+        o_steps = T if T <= 64 else 64
+        o_rate, o_s = _oracle_rate(sc, o_steps, act=act_np)
+        out[name] = {"particles": N, "steps": T, "ms_per_trajectory": round(ms, 4),
+                     "particle_steps_per_s": N * T / (ms * 1e-3), "knobs": knobs,
+                     "hbm_frac": round(5 * 48 * N * T / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 5),
+                     "oracle_1core": {"value": o_rate, "sample": f"first {o_steps} steps, {o_s:.2f} s"}}
+    sc = scenes.elastic3d_long()
+    o_rate, o_s = _oracle_rate(sc, 4)
+    out["elastic3d_long_oracle_1core"] = {"value": o_rate, "sample": f"all {sc.n_particles} particles, first 4 "
+                                                                     f"steps, fwd + reverse, {o_s:.1f} s"}
+    return out
+
+
+def tile_fallback(torch, rt, sc, knobs, window=64):
+    """Fraction of workgroup scatters of the forward pass that fall back to
+    global atomics (their stencils' box outgrew the LDS tile), over the first
+    and the last `window` steps of the trajectory, with particles sorted once
+    at step 0 (as the tape does): forward runs of T - window and T steps,
+    the second count minus the first."""
+    T = sc.steps
+    sim = rt.Simulator.for_scene(sc, knobs={**knobs, "tile_stats": 1})
+    act = None
+    if sc.n_act:
+        W = torch.as_tensor(sc.act_W, device="cuda")
+        b = torch.as_tensor(sc.act_b, device="cuda")
+        act = sim.actuation(W, b, sc.act_omega, T)
+    params = rt.params_for_scene(sc, act=act)
+    init = rt.state_for_scene(sc)
+    fin = rt.State.empty(sc.dim, sc.n_particles)
+    counts = {}
+    for n in (window, T - window, T):
+        sim.tile_stats()
+        tape = sim.tape(n, sc.ckpt_every if sc.ckpt_every and sc.ckpt_every < n else 0)
+        tape.forward(params, init, fin)
+        counts[n] = sim.tile_stats()
+        del tape
+    first = counts[window]
+    last = tuple(a - b for a, b in zip(counts[T], counts[T - window]))
+    frac = lambda c: round(c[1] / max(c[0] + c[1], 1), 4)  # noqa: E731
+    return {"window_steps": window, "first": {"lds": first[0], "fallback": first[1], "frac": frac(first)},
+            "last": {"lds": last[0], "fallback": last[1], "frac": frac(last)}}
 
 
 def run_corotated(args, torch, rt, scenes, knobs):
@@ -388,11 +569,13 @@ def run_robot3d(args, torch, rt, scenes, iters=3, name="robot3d"):
     secs = time.perf_counter() - t0
     if ctl.sim.check_errors():
         raise RuntimeError("robot3d: simulation error flags set")
+    fb = tile_fallback(torch, rt, sc, knobs)
     what = "3D actuated robot" if name == "robot3d" else "3D actuated robot beside weakly compressible liquid"
     return {"workload": f"{what}, 64^3 grid, {sc.n_particles} particles, {sc.n_act} actuators, "
                         f"{sc.steps} steps; one optimisation iteration = fwd + loss + bwd + weight update",
             "particle_steps_per_s": sc.n_particles * sc.steps * iters / secs,
-            "ms_per_iteration": secs * 1e3 / iters, "losses": [round(v, 6) for v in hist], "knobs": knobs}
+            "ms_per_iteration": secs * 1e3 / iters, "losses": [round(v, 6) for v in hist], "knobs": knobs,
+            "tile_fallback": fb}
 
 
 def run_smoke(args, torch, rt, scenes, tile=0, repeats=10):
@@ -449,11 +632,16 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-robot", action="store_true")
     ap.add_argument("--no-smoke", action="store_true")
+    ap.add_argument("--no-long", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default launch configuration")
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune.json"))
+    ap.add_argument("--tune-cache", default=TUNED,
+                    help="autotuner results (committed; shapes missing from it are tuned on the spot and added)")
     ap.add_argument("--knobs", default=None, help='launch configuration for the 3D workload as JSON, e.g. \'{"block": 256}\'')
     ap.add_argument("--profile", action="store_true",
                     help="3D workload only, then one calibration copy (for rocprofv3 counter runs)")
+    ap.add_argument("--profile-smoke", action="store_true",
+                    help="smoke workload only (--steps trajectories), for rocprofv3 runs")
     ap.add_argument("--profile-batched", action="store_true",
                     help="batched 2D workload only (--steps trajectories), then one calibration copy")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -475,6 +663,21 @@ def main():
     from paper_1910_00935_amd import runtime as rt
     from paper_1910_00935_amd import scenes
     torch.cuda.set_device(0)
+    if args.profile_smoke:
+        # The smoke workload's forward, loss and reverse, --steps times, for rocprofv3 runs.
+        sc = scenes.smoke()
+        sim = rt.SmokeSim.for_scene(sc)
+        init = rt.smoke_state(sc)
+        target = torch.as_tensor(sc.target, device="cuda")
+        seed = torch.empty(3, sc.n, sc.n, device="cuda")
+        grad = torch.zeros(3, sc.n, sc.n, device="cuda")
+        for _ in range(args.steps):
+            sim.forward(init)
+            sim.loss(target, seed)
+            sim.backward(seed, grad)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": "smoke", "flags": sim.check_errors()}), flush=True)
+        return
     if args.profile_batched:
         # One batched 2D trajectory (fwd + loss + bwd) per step, for rocprofv3 runs.
         sc = scenes.batched2d()
@@ -516,6 +719,12 @@ def main():
     if not args.no_batched:
         print("[bench] batched 2D workload", flush=True)
         out["batched"] = run_batched(args, torch, rt, scenes)
+    if not args.no_configs:
+        print("[bench] 2D workloads", flush=True)
+        out["configs"] = run_configs(args, torch, rt, scenes)
+    if not args.no_long:
+        print("[bench] long 3D workload", flush=True)
+        out["elastic3d_long"] = run_elastic3d_long(args, torch, rt, scenes)
     if not args.no_robot:
         print("[bench] 3D robot controller optimisation", flush=True)
         out["robot3d"] = run_robot3d(args, torch, rt, scenes)
