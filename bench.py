@@ -478,7 +478,7 @@ def run_configs(args, torch, rt, scenes, repeats=5):
         if sim.check_errors():
             raise RuntimeError(f"{name}: simulation error flags set")
         o_steps = T if T <= 64 else 64
-        o_rate, o_s = _oracle_rate(sc, o_steps, act=act_np)
+        o_rate, o_s = _oracle_rate(sc, o_steps, act=None if act_np is None else act_np[:o_steps])
         out[name] = {"particles": N, "steps": T, "ms_per_trajectory": round(ms, 4),
                      "particle_steps_per_s": N * T / (ms * 1e-3), "knobs": knobs,
                      "hbm_frac": round(5 * 48 * N * T / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 5),

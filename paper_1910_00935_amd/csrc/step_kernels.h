@@ -917,23 +917,32 @@ __device__ __forceinline__ bool tile_node_interior(const int (&c)[D], int n, int
   return in;
 }
 
-// Adds the non-zero nodes of a fixed-point tile into the global grid.
+// Adds the non-zero entries of a fixed-point tile into the global grid. Lanes
+// run over (node, component) pairs, component fastest, so one atomic
+// instruction covers a few runs of consecutive nodes in a handful of cache
+// lines. With one node per lane and one instruction per component, each
+// instruction spread over a dozen or more lines, and the flush atomics of all
+// workgroups (which overlap at box borders) went on draining for several
+// microseconds after the last workgroup had ended.
 template <int D, int NC>
 __device__ __forceinline__ void tile_flush64(const Tile<D>& T, const long long* tile, float4* g, int n,
                                              int threads) {
-  for (int q = threadIdx.x; q < T.n; q += threads) {
-    long long v[NC];
-    bool nz = false;
+  // Four entries per thread per pass: their LDS reads are issued together.
+  const int total = NC * T.n;
+  for (int j0 = threadIdx.x; j0 < total; j0 += 4 * threads) {
+    long long v[4];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      v[c] = tile[c * kTileCap<D> + q];
-      nz = nz || (v[c] != 0);
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + u * threads;
+      const int q = j / NC;
+      v[u] = j < total ? tile[(j - q * NC) * kTileCap<D> + q] : 0;
     }
-    if (nz) {
-      float* dst = reinterpret_cast<float*>(g + tile_global_index<D>(T, q, n));
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        if (v[c] != 0) atomic_add_f32(dst + c, from_fixed(v[c], T.e));
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + u * threads;
+      const int q = j / NC;
+      if (v[u] != 0)
+        atomic_add_f32(reinterpret_cast<float*>(g + tile_global_index<D>(T, q, n)) + (j - q * NC), from_fixed(v[u], T.e));
     }
   }
 }

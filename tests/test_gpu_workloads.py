@@ -143,7 +143,12 @@ def test_elastic3d_long_reverse_segment(start):
     """One 32-step segment of the 128-step reverse pass at full size: the GPU
     tape runs from the oracle's state at `start` (rounded to FP32) and is
     seeded with the oracle's dL/dstate(start + 32); dL/dstate(start) and the
-    segment's dL/dE are gated against the oracle's."""
+    segment's dL/dE are gated against the oracle's. A segment's dL/dE is a
+    partial sum of the trajectory's dL/dE whose steps change sign (over steps
+    64..95 it sums to 8.9e-4 against 7.8e-3 and 1.9e-2 for the neighbouring
+    segments and 3.6e-2 in all), so its error is gated against the size of the
+    whole 128-step dL/dE, the gradient the relative gate applies to; the error
+    relative to the segment's own sum is logged."""
     c = _c4()
     sc = c["scene"]
     gN, eN = _c4_grad(start + C4_CHUNK)
@@ -159,7 +164,9 @@ def test_elastic3d_long_reverse_segment(start):
         r[f"g{name}_cos"] = cos(g["g0"][k], o[k])
         r[f"g{name}_rel"] = rel(g["g0"][k], o[k])
         r[f"g{name}_max_rms"] = max_rms(g["g0"][k], o[k])
-    r["gE_rel"] = abs(g["gE"][0] - (e0 - eN)) / abs(e0 - eN)
+    e_all = _c4_grad(0)[1]
+    r["gE_rel_segment"] = abs(g["gE"][0] - (e0 - eN)) / abs(e0 - eN)
+    r["gE_rel"] = abs(g["gE"][0] - (e0 - eN)) / abs(e_all)
     log(f"[parity] elastic3d_long reverse {start + C4_CHUNK}->{start}: " + ", ".join(f"{k}={v:.3g}" for k, v in r.items()))
     for name in "xvCF":
         assert r[f"g{name}_cos"] >= G_COS and r[f"g{name}_rel"] <= G_REL and r[f"g{name}_max_rms"] <= G_MAX_RMS, (name, r)
