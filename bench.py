@@ -144,11 +144,48 @@ def run_elastic3d(args, torch, rt, scenes):
         # Context for frac: a streaming launch of the same byte count, no dependent work.
         "copy_same_bytes": copy_ceiling(torch, dom["bytes"]),
     }
+    # Workgroup wall clocks of one more trajectory (replayed graph, as timed):
+    # how much of each launch is workgroup work and how much lies between launches.
+    clk = wg_clock_summary(torch, sim, step, rows=2 * T + 8)
+    for k, v in clk.items():
+        roofline["kernels"][k].update(v)
     return {
         "value": value, "ms_per_step": secs * 1e3 / args.steps, "N": N, "T": T, "roofline": roofline, "knobs": knobs,
         "whole_step_hbm_frac": round((5 * S * 4 * N * T * args.steps / secs) / (HBM_PEAK_GBS * 1e9), 4),
         "gpu_event_ms": gpu_ms, "wall_s": wall,
     }
+
+
+def wg_clock_summary(torch, sim, run, rows):
+    """Runs `run` once with workgroup wall clocks bound and summarises, per step
+    kernel, medians over its launches of: the span from the first workgroup's
+    start to the last one's end, the median workgroup's duration, and the gap
+    from the last workgroup's end to the first start of the next launch of the
+    same kernel (consecutive launches only)."""
+    import numpy as np
+    from paper_1910_00935_amd import _lib as L
+    sim.bind_wg_clock(sim.wg_clock_buffer(rows))
+    run()
+    torch.cuda.synchronize()
+    recs = sim.wg_clock()
+    sim.bind_wg_clock(None)
+    names = {L.MPM_KERNEL_FWD: "k_fwd", L.MPM_KERNEL_BWD: "k_bwd"}
+    out = {}
+    for kind, name in names.items():
+        spans, wgmed, gaps = [], [], []
+        for r, (k, st, en) in enumerate(recs):
+            if k != kind:
+                continue
+            spans.append(en.max() - st.min())
+            wgmed.append(np.median(en - st))
+            if r + 1 < len(recs) and recs[r + 1][0] == kind:
+                gaps.append(recs[r + 1][1].min() - en.max())
+        if spans:
+            out[name] = {"wg_span_us": round(float(np.median(spans)), 3),
+                         "wg_median_us": round(float(np.median(wgmed)), 3),
+                         "gap_to_next_us": round(float(np.median(gaps)), 3) if gaps else None,
+                         "clocked_launches": len(spans)}
+    return out
 
 
 COPY_MIB = 64  # calibration copy: reads and writes exactly this many MiB

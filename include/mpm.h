@@ -218,6 +218,27 @@ mpm_status mpm_kernel_stats(mpm_ctx* ctx, int32_t kernel, double* total_ms, int6
  * counts since the previous call and resets them. */
 mpm_status mpm_tile_stats(mpm_ctx* ctx, void* stream, int64_t* lds_scatters, int64_t* fallback_scatters);
 
+/* Workgroup wall clocks (measurement support, not part of the method). Binds
+ * a caller-owned device buffer of `bytes` bytes (or turns the clocks off when
+ * buf is null) and restarts the launch count. Every later launch of a step
+ * kernel (enqueued directly or captured into a graph; not the persistent form)
+ * takes the next row of the buffer, while rows are left: row r, workgroup w
+ * holds two uint64 stamps of the device's constant-rate clock at
+ * ((uint64_t*)buf)[2 * (r * stride + w)], taken when the workgroup starts and
+ * when all its waves have finished. stride = 2 * (workgroups of one particle
+ * pass) at bind time; a launch wider than that (after a launch-shape knob
+ * change) is not stamped. A replayed graph writes the rows its capture took.
+ * MPM_E_ARG on a null ctx or a buffer smaller than one row. */
+mpm_status mpm_wg_clock_bind(mpm_ctx* ctx, void* buf, size_t bytes);
+
+/* Rows taken since the last bind: *launches rows; for row r < max_rows,
+ * kind[r] (MPM_KERNEL_FWD / MPM_KERNEL_BWD) and wgs[r] (its workgroups); the
+ * row stride in workgroups (with no buffer bound: the stride a bind would
+ * take now) and the clock's rate in kHz (the device's wall clock rate). Any
+ * output pointer may be null. */
+mpm_status mpm_wg_clock_info(const mpm_ctx* ctx, int32_t* launches, int32_t* stride, int32_t* kind, int32_t* wgs,
+                             int32_t max_rows, int32_t* rate_khz);
+
 /* One forward step, state `in` (step `step`) -> `out` (step + 1), in the
  * caller's particle order: clear_grid, compute_actuation (row `step` of
  * params->act), p2g, grid_op, g2p (Appendix D.1 stage order). `in` and `out`

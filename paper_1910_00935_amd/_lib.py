@@ -101,6 +101,10 @@ _SIGNATURES = {
                                    ctypes.POINTER(ctypes.c_int64)]),
     "mpm_tile_stats": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_int64)]),
+    "mpm_wg_clock_bind": (c_int32, [c_void_p, c_void_p, c_size_t]),
+    "mpm_wg_clock_info": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
+                                    ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), c_int32,
+                                    ctypes.POINTER(c_int32)]),
     # include/smoke.h
     "smoke_tape_bytes": (c_size_t, [ctypes.POINTER(smoke_desc)]),
     "smoke_workspace_bytes": (c_size_t, [ctypes.POINTER(smoke_desc)]),
@@ -243,6 +247,24 @@ def mpm_tile_stats(ctx, stream):
     b = ctypes.c_int64(0)
     call("mpm_tile_stats", ctx, c_void_p(stream), ctypes.byref(a), ctypes.byref(b))
     return int(a.value), int(b.value)
+
+
+def mpm_wg_clock_bind(ctx, ptr, nbytes):
+    call("mpm_wg_clock_bind", ctx, c_void_p(ptr), c_size_t(nbytes))
+
+
+def mpm_wg_clock_info(ctx):
+    """(kinds, workgroups per row, row stride, clock rate in kHz) of the rows
+    taken since the last bind."""
+    n = c_int32(0)
+    call("mpm_wg_clock_info", ctx, ctypes.byref(n), None, None, None, 0, None)
+    rows = n.value
+    kind = (c_int32 * max(rows, 1))()
+    wgs = (c_int32 * max(rows, 1))()
+    stride = c_int32(0)
+    rate = c_int32(0)
+    call("mpm_wg_clock_info", ctx, ctypes.byref(n), ctypes.byref(stride), kind, wgs, rows, ctypes.byref(rate))
+    return list(kind)[:rows], list(wgs)[:rows], int(stride.value), int(rate.value)
 
 
 def mpm_check_errors(ctx, stream):

@@ -131,6 +131,17 @@ struct mpm_ctx {
   hipStream_t span_st = nullptr;
   double ev_ms[2] = {0.0, 0.0};
   long ev_count[2] = {0, 0};
+  // Workgroup wall clocks (mpm_wg_clock_bind): caller buffer of clk_slots
+  // launch rows of clk_stride workgroups; launches take rows in enqueue order
+  // (clk_next), their kernel kind and workgroup count kept in clk_kind and
+  // clk_wgs. clk_epoch changes at every bind (part of the graph key, so a
+  // sequence is captured again with its new rows).
+  unsigned long long* clk = nullptr;
+  long clk_slots = 0;
+  int clk_stride = 0;
+  int clk_epoch = 0;
+  mutable int clk_next = 0;
+  mutable std::vector<int> clk_kind, clk_wgs;
 
   template <class T>
   T* at(Region r) const {
@@ -387,6 +398,17 @@ struct SpanGuard {
   ~SpanGuard() { span_close(c); }
 };
 
+// Gives a launch of `wgs` workgroups of kernel `kind` its wall-clock row, if
+// clocks are bound and a row of the right width is left.
+void clock_row(const mpm_ctx& c, StepConsts& k, int kind, int wgs) {
+  if (!c.clk || wgs > c.clk_stride || c.clk_next >= c.clk_slots) return;
+  k.wgclk = c.clk;
+  k.clk_stride = c.clk_stride;
+  k.clk_slot = c.clk_next++;
+  c.clk_kind.push_back(kind);
+  c.clk_wgs.push_back(wgs);
+}
+
 template <int D, int LPP>
 mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& args, hipStream_t st, bool timed) {
   FwdArgs a = args;
@@ -397,6 +419,7 @@ mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& args, hipStream_t st, boo
     c.rec_fwd->push_back(a);
     return MPM_OK;
   }
+  clock_row(c, a.k, MPM_KERNEL_FWD, c.n_blocks);
   if (timed) span_step(c, 0, st);
   const bool pre = LPP == 1 && c.presum;
   if (c.model == 1) {
@@ -425,6 +448,7 @@ mpm_status launch_bwd(const mpm_ctx& c, const BwdArgs& args, hipStream_t st) {
     c.rec_bwd->push_back(a);
     return MPM_OK;
   }
+  clock_row(c, a.k, MPM_KERNEL_BWD, nb);
   span_step(c, 1, st);
   const bool pre = LPP == 1 && c.presum;
   if (c.model == 1) {
@@ -1348,7 +1372,8 @@ std::vector<uintptr_t> graph_key(const mpm_tape* tape, int kind, const mpm_param
   const mpm_ctx& c = *tape->ctx;
   std::vector<uintptr_t> k = {uintptr_t(kind), reinterpret_cast<uintptr_t>(c.ws), reinterpret_cast<uintptr_t>(tape->mem),
                               uintptr_t(c.block), uintptr_t(c.lds), uintptr_t(c.split_c), uintptr_t(c.remap), uintptr_t(c.rotate), uintptr_t(c.lanes),
-                              uintptr_t(c.part), uintptr_t(c.presum),
+                              uintptr_t(c.part), uintptr_t(c.presum), reinterpret_cast<uintptr_t>(c.clk),
+                              uintptr_t(c.clk_epoch),
                               reinterpret_cast<uintptr_t>(p->E), reinterpret_cast<uintptr_t>(p->nu),
                               reinterpret_cast<uintptr_t>(p->vol), reinterpret_cast<uintptr_t>(p->rho),
                               reinterpret_cast<uintptr_t>(p->act_id), reinterpret_cast<uintptr_t>(p->act),
@@ -1505,6 +1530,46 @@ mpm_status mpm_tile_stats(mpm_ctx* ctx, void* stream, int64_t* lds_scatters, int
   HIP_TRY(hipMemcpy(ctx->at<unsigned long long>(R_TSTATS), zero, sizeof(zero), hipMemcpyHostToDevice));
   *lds_scatters = int64_t(v[0]);
   *fallback_scatters = int64_t(v[1]);
+  return MPM_OK;
+}
+
+mpm_status mpm_wg_clock_bind(mpm_ctx* ctx, void* buf, size_t bytes) {
+  if (!ctx) return MPM_E_ARG;
+  ctx->clk_next = 0;
+  ctx->clk_kind.clear();
+  ctx->clk_wgs.clear();
+  ++ctx->clk_epoch;
+  if (!buf) {
+    ctx->clk = nullptr;
+    ctx->clk_slots = 0;
+    return MPM_OK;
+  }
+  if (ctx->n_blocks <= 0) return MPM_E_STATE;
+  const int stride = 2 * ctx->n_blocks;
+  const size_t row = size_t(stride) * 2 * sizeof(unsigned long long);
+  if (bytes < row || reinterpret_cast<uintptr_t>(buf) % 8) return MPM_E_ARG;
+  ctx->clk = static_cast<unsigned long long*>(buf);
+  ctx->clk_stride = stride;
+  ctx->clk_slots = long(bytes / row);
+  return MPM_OK;
+}
+
+mpm_status mpm_wg_clock_info(const mpm_ctx* ctx, int32_t* launches, int32_t* stride, int32_t* kind, int32_t* wgs,
+                             int32_t max_rows, int32_t* rate_khz) {
+  if (!ctx) return MPM_E_ARG;
+  if (launches) *launches = ctx->clk_next;
+  if (stride) *stride = ctx->clk ? ctx->clk_stride : 2 * ctx->n_blocks;
+  const int n = std::min<int>(std::max<int>(max_rows, 0), ctx->clk_next);
+  for (int r = 0; r < n; ++r) {
+    if (kind) kind[r] = ctx->clk_kind[r];
+    if (wgs) wgs[r] = ctx->clk_wgs[r];
+  }
+  if (rate_khz) {
+    int dev = 0, rate = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev));
+    *rate_khz = rate;
+  }
   return MPM_OK;
 }
 

@@ -77,6 +77,12 @@ struct StepConsts {
   unsigned* err;
   unsigned long long* tstats;  // null, or [2]: scatters accumulated in an LDS tile, scatters that fell back
                                // to global atomics (one count per workgroup and scatter)
+  // Workgroup wall clock (mpm_wg_clock_bind), or null: entry and exit stamps of
+  // the constant-rate device clock of every workgroup of this launch, at
+  // wgclk[2 * (clk_slot * clk_stride + workgroup)] (clk_slot < 0: not stamped).
+  unsigned long long* wgclk = nullptr;
+  int clk_slot = -1;
+  int clk_stride = 0;
 };
 
 struct FwdArgs {
@@ -1379,6 +1385,17 @@ __device__ __forceinline__ void zero_tile64(long long* tile, int threads) {
   for (int q = threadIdx.x; q < NC * kTileCap<D>; q += threads) tile[q] = 0;
 }
 
+// Entry stamp t0 and exit stamp of this workgroup's wall clock, the exit taken
+// once every wave of the workgroup has finished its work.
+__device__ __forceinline__ void stamp_workgroup(const StepConsts& k, unsigned long long t0) {
+  __syncthreads();
+  if (threadIdx.x == 0 && k.clk_slot >= 0) {
+    unsigned long long* p = k.wgclk + 2 * (size_t(k.clk_slot) * size_t(k.clk_stride) + blockIdx.x);
+    p[0] = t0;
+    p[1] = wall_clock64();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
@@ -1503,7 +1520,9 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int wgi, FwdShared<D
 template <int D, int LPP, int M, bool PRE = false>
 __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   __shared__ FwdShared<D> sh;
+  const unsigned long long t0 = a.k.wgclk ? wall_clock64() : 0ull;
   fwd_block<D, LPP, M, false, PRE>(a, int(blockIdx.x), sh);
+  if (a.k.wgclk) stamp_workgroup(a.k, t0);
 }
 
 // Sum `val` over the live lanes of the wavefront that share `key`, and add
@@ -1857,7 +1876,9 @@ __device__ __forceinline__ void bwd_block(const BwdArgs& a, int wgi, BwdShared<D
 template <int D, int LPP, int M, bool PRE = false>
 __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   __shared__ BwdShared<D> sh;
+  const unsigned long long t0 = a.k.wgclk ? wall_clock64() : 0ull;
   bwd_block<D, LPP, M, false, PRE>(a, int(blockIdx.x), sh);
+  if (a.k.wgclk) stamp_workgroup(a.k, t0);
 }
 
 // Persistent forms (knob "persist"): the step launches of a recorded tape

@@ -188,6 +188,31 @@ class Simulator:
         """(LDS-tile scatters, fallback scatters) since the last call (knob "tile_stats")."""
         return L.mpm_tile_stats(self.ctx, _stream())
 
+    def bind_wg_clock(self, buf):
+        """Workgroup wall clocks of the following step launches into `buf` (a
+        CUDA int64 tensor, kept by the simulator), or off with None."""
+        self._clk = buf
+        if buf is None:
+            L.mpm_wg_clock_bind(self.ctx, 0, 0)
+        else:
+            L.mpm_wg_clock_bind(self.ctx, buf.data_ptr(), buf.numel() * buf.element_size())
+
+    def wg_clock_buffer(self, rows):
+        """A zeroed device buffer for `rows` launches of workgroup wall clocks."""
+        stride = L.mpm_wg_clock_info(self.ctx)[2]
+        return torch.zeros(rows * stride * 2, dtype=torch.int64, device="cuda")
+
+    def wg_clock(self):
+        """Rows taken since bind_wg_clock, in enqueue order: (kind, start, end)
+        with the start and end of every workgroup in microseconds (numpy)."""
+        kinds, wgs, stride, rate = L.mpm_wg_clock_info(self.ctx)
+        if getattr(self, "_clk", None) is None or not kinds:
+            return []
+        torch.cuda.synchronize()
+        a = self._clk[: len(kinds) * stride * 2].view(len(kinds), stride, 2).cpu().numpy()
+        us = 1e3 / rate
+        return [(k, a[r, :w, 0] * us, a[r, :w, 1] * us) for r, (k, w) in enumerate(zip(kinds, wgs))]
+
     def check_errors(self):
         """Synchronises and returns the device error flags (MPM_FLAG_* bits)."""
         st, flags = L.mpm_check_errors(self.ctx, _stream())
