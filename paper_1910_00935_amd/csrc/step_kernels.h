@@ -43,13 +43,17 @@
 
 namespace mpm {
 
-// Nodes per LDS tile: 512 in 3D, 768 in 2D. A workgroup whose box exceeds it
+// Nodes per LDS tile: 1024 in 3D, 768 in 2D. A workgroup whose box exceeds it
 // falls back to global atomics, which costs far more than the LDS it would
 // have used: in the batched 2D workload at 256 particles per workgroup about
 // 5 % of the boxes exceed 512 nodes and under 1 % exceed 768, and 768 still
-// leaves the kernels' LDS use balanced with their register use.
+// leaves the kernels' LDS use balanced with their register use. In 3D, 512
+// nodes cover the lattice workloads (boxes of ~245 nodes) but not the robot
+// beside the liquid once the liquid spreads (11 % of late scatters fell back,
+// and its trajectories took twice as long); 1024 covers all of them.
 template <int D>
-constexpr int kTileCap = (D == 3) ? 512 : 768;
+constexpr int kTileCap = (D == 3) ? 1024 : 768;
+static_assert((3 * kTileCap<2>) % 2 == 0 && (3 * kTileCap<3>) % 2 == 0, "zero_tile64 clears whole 16-byte pairs");
 
 struct StepConsts {
   int N;          // particles
@@ -1382,7 +1386,9 @@ __device__ __forceinline__ void p2g_phase(const StepConsts& k, bool live, int i,
 // next block reduction's barrier orders it before the scatter).
 template <int D, int NC>
 __device__ __forceinline__ void zero_tile64(long long* tile, int threads) {
-  for (int q = threadIdx.x; q < NC * kTileCap<D>; q += threads) tile[q] = 0;
+  // 16-byte stores: two entries per store (the tiles are 16-byte aligned).
+  int4* t = reinterpret_cast<int4*>(tile);
+  for (int q = threadIdx.x; q < NC * kTileCap<D> / 2; q += threads) t[q] = make_int4(0, 0, 0, 0);
 }
 
 // Entry stamp t0 and exit stamp of this workgroup's wall clock, the exit taken
@@ -1446,7 +1452,7 @@ struct LaneMap {
 // LDS of the forward step body.
 template <int D>
 struct FwdShared {
-  long long tile64[(D + 1) * kTileCap<D>];  // P2G scatter tile (fixed point)
+  alignas(16) long long tile64[(D + 1) * kTileCap<D>];  // P2G scatter tile (fixed point)
   float vtile[D * kTileCap<D>];              // G2P velocity tile
   int red[64];
 };
@@ -1545,7 +1551,7 @@ template <int D>
 struct BwdShared {
   float tA[(D + 1) * kTileCap<D>];      // phase A: adjoint tile (P*, m*)
   float tV[D * kTileCap<D>];            // phase B: velocity tile
-  long long tS[(D + 1) * kTileCap<D>];  // scatter tile: phase B (adjoint grid), phase C (grid)
+  alignas(16) long long tS[(D + 1) * kTileCap<D>];  // scatter tile: phase B (adjoint grid), phase C (grid)
   int red[64];
 };
 
