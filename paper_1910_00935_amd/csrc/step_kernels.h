@@ -1391,6 +1391,33 @@ __device__ __forceinline__ void zero_tile64(long long* tile, int threads) {
   for (int q = threadIdx.x; q < NC * kTileCap<D> / 2; q += threads) t[q] = make_int4(0, 0, 0, 0);
 }
 
+// Brings the launch's kernel arguments into the scalar cache in one round
+// trip. The step kernels read their argument struct field by field where each
+// branch needs it, and every read of a field not read before waits for memory:
+// about a dozen dependent round trips before the reverse kernel issues its
+// first global load. Here every whole 64-byte line of the struct is loaded at
+// once (into a scratch register block, waited for inside the same statement),
+// so those reads then hit the cache.
+template <int BYTES>
+__device__ __forceinline__ void warm_kernargs() {
+  typedef int v16i __attribute__((ext_vector_type(16)));
+  const unsigned long long base = reinterpret_cast<unsigned long long>(__builtin_amdgcn_kernarg_segment_ptr());
+  v16i sink;
+#define KA_LINE(off) "s_load_dwordx16 %0, %1, " #off "\n"
+  if constexpr (BYTES / 64 >= 9) {
+    asm volatile(KA_LINE(0x0) KA_LINE(0x40) KA_LINE(0x80) KA_LINE(0xc0) KA_LINE(0x100) KA_LINE(0x140)
+                 KA_LINE(0x180) KA_LINE(0x1c0) KA_LINE(0x200) "s_waitcnt lgkmcnt(0)"
+                 : "=&s"(sink) : "s"(base));
+  } else if constexpr (BYTES / 64 >= 5) {
+    asm volatile(KA_LINE(0x0) KA_LINE(0x40) KA_LINE(0x80) KA_LINE(0xc0) KA_LINE(0x100) "s_waitcnt lgkmcnt(0)"
+                 : "=&s"(sink) : "s"(base));
+  } else {
+    return;
+  }
+#undef KA_LINE
+  asm volatile("" ::"s"(sink));
+}
+
 // Entry stamp t0 and exit stamp of this workgroup's wall clock, the exit taken
 // once every wave of the workgroup has finished its work.
 __device__ __forceinline__ void stamp_workgroup(const StepConsts& k, unsigned long long t0) {
@@ -1526,6 +1553,7 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int wgi, FwdShared<D
 template <int D, int LPP, int M, bool PRE = false>
 __global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
   __shared__ FwdShared<D> sh;
+  warm_kernargs<sizeof(FwdArgs)>();
   const unsigned long long t0 = a.k.wgclk ? wall_clock64() : 0ull;
   fwd_block<D, LPP, M, false, PRE>(a, int(blockIdx.x), sh);
   if (a.k.wgclk) stamp_workgroup(a.k, t0);
@@ -1882,6 +1910,7 @@ __device__ __forceinline__ void bwd_block(const BwdArgs& a, int wgi, BwdShared<D
 template <int D, int LPP, int M, bool PRE = false>
 __global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
   __shared__ BwdShared<D> sh;
+  warm_kernargs<sizeof(BwdArgs)>();
   const unsigned long long t0 = a.k.wgclk ? wall_clock64() : 0ull;
   bwd_block<D, LPP, M, false, PRE>(a, int(blockIdx.x), sh);
   if (a.k.wgclk) stamp_workgroup(a.k, t0);
