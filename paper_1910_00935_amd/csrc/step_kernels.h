@@ -1627,11 +1627,15 @@ __device__ __forceinline__ void bwd_block(const BwdArgs& a, int wgi, BwdShared<D
     if (err) atomicOr(k.err, err);
     return;
   }
-  // Every independent global read is issued first: dL/dstate(s+1) (seed, or
-  // state s+1 and the x*, F* partials), phase B's inputs (x, F of state s and
-  // C of state s+1), then the gather boxes recorded by the scatters into grid
-  // s+1 (phase A) and grid s (phase B) and both tile loads, so no phase waits
-  // for a read it could have started earlier.
+  // Every independent global read is issued first: the gather boxes recorded
+  // by the scatters into grid s+1 (phase A) and grid s (phase B), read before
+  // the particle loads are issued so that their round trip overlaps those;
+  // dL/dstate(s+1) (seed, or state s+1 and the x*, F* partials), phase B's
+  // inputs (x, F of state s and C of state s+1); then both tile loads, so no
+  // phase waits for a read it could have started earlier.
+  Tile<D> TA = empty_tile<D>(), TB = empty_tile<D>();
+  if (a.a_mode == 1 && a.boxA_in) TA = recorded_tile<D, P>(a.boxA_in, wg, sc, one_scene, k.lds, k.n);
+  if (!a.final_out && a.boxB_in) TB = recorded_tile<D, P>(a.boxB_in, wg, sc, one_scene, k.lds, k.n);
   float gx[D] = {}, gv[D] = {}, gC[D][D] = {}, gF[D][D] = {};
   PState<D> p;  // phase A: state s+1
   if (live) {
@@ -1670,9 +1674,6 @@ __device__ __forceinline__ void bwd_block(const BwdArgs& a, int wgi, BwdShared<D
     }
   }
   if (!a.final_out && k.lds) zero_tile64<D, D>(tS, k.threads);
-  Tile<D> TA = empty_tile<D>(), TB = empty_tile<D>();
-  if (a.a_mode == 1 && a.boxA_in) TA = recorded_tile<D, P>(a.boxA_in, wg, sc, one_scene, k.lds, k.n);
-  if (!a.final_out && a.boxB_in) TB = recorded_tile<D, P>(a.boxB_in, wg, sc, one_scene, k.lds, k.n);
   if (TA.on) tile_load_adj<D>(k, TA, a.gA + long(sc) * k.nodes, a.aA + long(sc) * k.nodes, tA);
   if (TB.on) tile_load_vel<D>(k, TB, a.gB + long(sc) * k.nodes, tV);
 
