@@ -1151,8 +1151,9 @@ constexpr int kTileBatch = 4;
 // Velocity tile: grid_op applied once per node of the box as it is staged
 // (components 0..D-1 = v), so gathers read v instead of forming P / m per visit.
 template <int D>
-__device__ __forceinline__ void tile_load_vel(const StepConsts& k, const Tile<D>& T, const float4* g, float* tile) {
-  for (int q0 = threadIdx.x; q0 < T.n; q0 += kTileBatch * k.threads) {
+__device__ __forceinline__ void tile_load_vel(const StepConsts& k, const Tile<D>& T, const float4* g, float* tile,
+                                              int first = 0) {
+  for (int q0 = first + threadIdx.x; q0 < T.n; q0 += kTileBatch * k.threads) {
     float4 gm[kTileBatch];
 #pragma unroll
     for (int r = 0; r < kTileBatch; ++r) {
@@ -1179,8 +1180,8 @@ __device__ __forceinline__ void tile_load_vel(const StepConsts& k, const Tile<D>
 // = P*, component D = m*), from the grid (m, P) and the adjoint grid (v*).
 template <int D>
 __device__ __forceinline__ void tile_load_adj(const StepConsts& k, const Tile<D>& T, const float4* g,
-                                              const float4* ad, float* tile) {
-  for (int q0 = threadIdx.x; q0 < T.n; q0 += kTileBatch * k.threads) {
+                                              const float4* ad, float* tile, int first = 0) {
+  for (int q0 = first + threadIdx.x; q0 < T.n; q0 += kTileBatch * k.threads) {
     float4 gm[kTileBatch], vb4[kTileBatch];
 #pragma unroll
     for (int r = 0; r < kTileBatch; ++r) {
@@ -1206,6 +1207,57 @@ __device__ __forceinline__ void tile_load_adj(const StepConsts& k, const Tile<D>
       }
     }
   }
+}
+
+// First node of each thread of a gather tile, read outside any loop. Behind a
+// loop the compiler waits for most loads issued before the loop (its
+// counter-based waits are conservative at loop headers), so a tile load in a
+// loop only starts once the particle loads issued before it have landed; read
+// straight-line, the tile's round trip overlaps theirs. Boxes of more nodes
+// than threads read the rest with tile_load_vel / tile_load_adj from
+// `k.threads` on.
+template <int D>
+struct TileFirst {
+  bool on;
+  int c[D];
+  float4 g, v;
+};
+
+template <int D>
+__device__ __forceinline__ TileFirst<D> tile_first_issue(const StepConsts& k, const Tile<D>& T, const float4* g,
+                                                         const float4* ad) {
+  TileFirst<D> f;
+  const int q = threadIdx.x;
+  f.on = T.on && q < T.n;
+  f.g = make_float4(0.f, 0.f, 0.f, 0.f);
+  f.v = f.g;
+  if (f.on) {
+    const int gi = tile_node<D>(T, q, k.n, f.c);
+    f.g = g[gi];
+    if (ad) f.v = ad[gi];
+  }
+  return f;
+}
+
+// Velocity tile entry of tile_first_issue (grid_op applied).
+template <int D>
+__device__ __forceinline__ void tile_first_vel(const StepConsts& k, const TileFirst<D>& f, float* tile) {
+  if (!f.on) return;
+  float v[D];
+  grid_vel<D>(tile_node_interior<D>(f.c, k.n, k.bound) && f.g.x > 0.0f, f.g, k.gdt, v);
+#pragma unroll
+  for (int a = 0; a < D; ++a) tile[a * kTileCap<D> + threadIdx.x] = v[a];
+}
+
+// Adjoint tile entry of tile_first_issue (grid_op* applied).
+template <int D>
+__device__ __forceinline__ void tile_first_adj(const StepConsts& k, const TileFirst<D>& f, float* tile) {
+  if (!f.on) return;
+  float Pb[D], mb;
+  grid_adj<D>(tile_node_interior<D>(f.c, k.n, k.bound) && f.g.x > 0.0f, f.g, f.v, Pb, mb);
+#pragma unroll
+  for (int a = 0; a < D; ++a) tile[a * kTileCap<D> + threadIdx.x] = Pb[a];
+  tile[D * kTileCap<D> + threadIdx.x] = mb;
 }
 
 // p2g* with grid_op* folded in: accumulates into gx, gv, Abar from grid (m, P)
@@ -1519,7 +1571,8 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int wgi, FwdShared<D
   const float4* g = a.grid_in + long(sc) * k.nodes;
   if (a.do_g2p && a.box_in) {
     T = recorded_tile<D, P>(a.box_in, wgi, sc, one_scene, k.lds, k.n);
-    if (T.on) tile_load_vel<D>(k, T, g, vtile);
+    tile_first_vel<D>(k, tile_first_issue<D>(k, T, g, nullptr), vtile);
+    if (T.on && T.n > k.threads) tile_load_vel<D>(k, T, g, vtile, k.threads);
   }
   if (a.do_g2p) {
     Sten<D> st;
@@ -1674,8 +1727,19 @@ __device__ __forceinline__ void bwd_block(const BwdArgs& a, int wgi, BwdShared<D
     }
   }
   if (!a.final_out && k.lds) zero_tile64<D, D>(tS, k.threads);
-  if (TA.on) tile_load_adj<D>(k, TA, a.gA + long(sc) * k.nodes, a.aA + long(sc) * k.nodes, tA);
-  if (TB.on) tile_load_vel<D>(k, TB, a.gB + long(sc) * k.nodes, tV);
+  {
+    // Both gather tiles: the first node of each thread of both in one round
+    // trip (tile_first_issue), the rest after.
+    const float4* gA = a.gA + long(sc) * k.nodes;
+    const float4* aA = a.aA + long(sc) * k.nodes;
+    const float4* gB = a.gB + long(sc) * k.nodes;
+    const TileFirst<D> fA = tile_first_issue<D>(k, TA, gA, aA);
+    const TileFirst<D> fB = tile_first_issue<D>(k, TB, gB, nullptr);
+    tile_first_adj<D>(k, fA, tA);
+    tile_first_vel<D>(k, fB, tV);
+    if (TA.on && TA.n > k.threads) tile_load_adj<D>(k, TA, gA, aA, tA, k.threads);
+    if (TB.on && TB.n > k.threads) tile_load_vel<D>(k, TB, gB, tV, k.threads);
+  }
 
   // dL/dstate(s+1): gx, gv, gC, gF.
   double eb = 0.0, actb = 0.0;
