@@ -1143,6 +1143,24 @@ __device__ __forceinline__ void node_adj(const StepConsts& k, const Sten<D>& st,
   }
 }
 
+// The first NC components of a grid node (the rest zero), read with a load of
+// exactly NC floats. A float4 load whose unused components' registers the
+// compiler hands to other values while the load is in flight must be waited
+// for in full before those registers are written, and the in-order counter
+// makes that wait cover every load issued before it.
+template <int NC>
+__device__ __forceinline__ float4 load_node(const float4* p) {
+  if constexpr (NC == 4) {
+    return *p;
+  } else if constexpr (NC == 3) {
+    const float3 t = *reinterpret_cast<const float3*>(p);
+    return make_float4(t.x, t.y, t.z, 0.0f);
+  } else {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    return make_float4(t.x, t.y, 0.0f, 0.0f);
+  }
+}
+
 // Tile loads issue up to kTileBatch node loads per thread before using any,
 // so their latencies overlap (a box of up to kTileCap<D> nodes takes one round
 // trip at 128 or more threads per workgroup).
@@ -1159,7 +1177,7 @@ __device__ __forceinline__ void tile_load_vel(const StepConsts& k, const Tile<D>
     for (int r = 0; r < kTileBatch; ++r) {
       const int q = q0 + r * k.threads;
       int c[D];
-      if (q < T.n) gm[r] = g[tile_node<D>(T, q, k.n, c)];
+      if (q < T.n) gm[r] = load_node<D + 1>(g + tile_node<D>(T, q, k.n, c));
     }
 #pragma unroll
     for (int r = 0; r < kTileBatch; ++r) {
@@ -1189,8 +1207,8 @@ __device__ __forceinline__ void tile_load_adj(const StepConsts& k, const Tile<D>
       int c[D];
       if (q < T.n) {
         const int gi = tile_node<D>(T, q, k.n, c);
-        gm[r] = g[gi];
-        vb4[r] = ad[gi];
+        gm[r] = load_node<D + 1>(g + gi);
+        vb4[r] = load_node<D>(ad + gi);
       }
     }
 #pragma unroll
@@ -1233,8 +1251,8 @@ __device__ __forceinline__ TileFirst<D> tile_first_issue(const StepConsts& k, co
   f.v = f.g;
   if (f.on) {
     const int gi = tile_node<D>(T, q, k.n, f.c);
-    f.g = g[gi];
-    if (ad) f.v = ad[gi];
+    f.g = load_node<D + 1>(g + gi);
+    if (ad) f.v = load_node<D>(ad + gi);
   }
   return f;
 }
