@@ -1488,6 +1488,12 @@ __device__ __forceinline__ void warm_kernargs() {
   asm volatile("" ::"s"(sink));
 }
 
+// Waves per SIMD the reverse kernel is compiled for: in 2D the batched
+// workload is throughput-bound and four waves per SIMD (at most 128 registers)
+// beat three; in 3D the kernel needs its registers (two waves).
+template <int D>
+constexpr int kBwdWaves = (D == 2) ? 4 : 1;
+
 // Entry stamp t0 and exit stamp of this workgroup's wall clock, the exit taken
 // once every wave of the workgroup has finished its work.
 __device__ __forceinline__ void stamp_workgroup(const StepConsts& k, unsigned long long t0) {
@@ -1991,7 +1997,7 @@ __device__ __forceinline__ void bwd_block(const BwdArgs& a, int wgi, BwdShared<D
 }
 
 template <int D, int LPP, int M, bool PRE = false>
-__global__ void __launch_bounds__(256) k_bwd(BwdArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBwdWaves<D>))) k_bwd(BwdArgs a) {
   __shared__ BwdShared<D> sh;
   warm_kernargs<sizeof(BwdArgs)>();
   const unsigned long long t0 = a.k.wgclk ? wall_clock64() : 0ull;
