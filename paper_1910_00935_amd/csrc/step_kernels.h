@@ -1488,11 +1488,14 @@ __device__ __forceinline__ void warm_kernargs() {
   asm volatile("" ::"s"(sink));
 }
 
-// Waves per SIMD the reverse kernel is compiled for: in 2D the batched
-// workload is throughput-bound and four waves per SIMD (at most 128 registers)
-// beat three; in 3D the kernel needs its registers (two waves).
+// Waves per SIMD the step kernels are compiled for: in 2D the batched
+// workload is throughput-bound and four waves per SIMD for the reverse kernel
+// (at most 128 registers) beat three, six for the forward kernel (80
+// registers) beat five; in 3D the kernels need their registers and LDS.
 template <int D>
 constexpr int kBwdWaves = (D == 2) ? 4 : 1;
+template <int D>
+constexpr int kFwdWaves = (D == 2) ? 6 : 1;
 
 // Entry stamp t0 and exit stamp of this workgroup's wall clock, the exit taken
 // once every wave of the workgroup has finished its work.
@@ -1628,7 +1631,7 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int wgi, FwdShared<D
 // PRE: particles sorted by stencil base, LDS scatters summed over runs of
 // equal-base lanes first (knob "presum"; one lane per particle only).
 template <int D, int LPP, int M, bool PRE = false>
-__global__ void __launch_bounds__(256) k_fwd(FwdArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdWaves<D>))) k_fwd(FwdArgs a) {
   __shared__ FwdShared<D> sh;
   warm_kernargs<sizeof(FwdArgs)>();
   const unsigned long long t0 = a.k.wgclk ? wall_clock64() : 0ull;
