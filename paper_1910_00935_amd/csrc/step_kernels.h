@@ -1162,8 +1162,9 @@ __device__ __forceinline__ float4 load_node(const float4* p) {
 }
 
 // Tile loads issue up to kTileBatch node loads per thread before using any,
-// so their latencies overlap (a box of up to kTileCap<D> nodes takes one round
-// trip at 128 or more threads per workgroup).
+// so their latencies overlap (a full 3D tile of kTileCap<3> nodes takes one
+// round trip at 256 threads per workgroup). The step kernels read the first
+// nodes straight-line (tile_first_issue) and use these loops for the rest.
 constexpr int kTileBatch = 4;
 
 // Velocity tile: grid_op applied once per node of the box as it is staged
