@@ -1285,7 +1285,10 @@ template <int D, bool L, int S0>
 __device__ __forceinline__ void p2g_adj_body(const StepConsts& k, const Sten<D>& st, float mass, const float (&mv)[D],
                                              const float (&A)[D][D], const Nodes<D, L>& g, const Nodes<D, L>& ad,
                                              float (&gx)[D], float (&vb)[D], float (&Abar)[D][D]) {
-  float gxa[D] = {};
+  // d/dx_p of sum_i P*_i . (m v + A (x_i - x_p)) w_ip: the weight-gradient
+  // term per node, and -A^T sum_i w_ip P*_i once (the sum is wP, also the
+  // velocity adjoint).
+  float gxa[D] = {}, wP[D] = {};
   const AffineTab<D> mom(st, mv, A);  // m v + A (x_i - x_p)
   for_nodes<D, S0>(st, [&](int o0, int o1, int o2) {
     float Pb[D], mb;
@@ -1298,18 +1301,20 @@ __device__ __forceinline__ void p2g_adj_body(const StepConsts& k, const Sten<D>&
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       contrib += Pb[c] * mom.at(c, o0, o1, o2);
-      vb[c] += w * Pb[c];
+      wP[c] += w * Pb[c];
 #pragma unroll
       for (int b = 0; b < D; ++b) Abar[c][b] += w * Pb[c] * dl[b];
     }
 #pragma unroll
-    for (int e = 0; e < D; ++e) {
-      float AtP = 0.0f;
-#pragma unroll
-      for (int c = 0; c < D; ++c) AtP += A[c][e] * Pb[c];
-      gxa[e] += contrib * dw[e] - w * AtP;
-    }
+    for (int e = 0; e < D; ++e) gxa[e] += contrib * dw[e];
   });
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) gxa[e] -= A[c][e] * wP[c];
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) vb[c] += wP[c];
   quad_reduce<S0>(gxa);
   quad_reduce<S0>(vb);
   quad_reduce<S0>(Abar);
@@ -1346,7 +1351,9 @@ template <int D, int S0, bool PRE = false, class GA, class SA>
 __device__ __forceinline__ void g2p_adj_body(const StepConsts& k, const Sten<D>& st, const float (&vt)[D],
                                              const float (&Bm)[D][D], const GA& g, const SA& ad, float (&px)[D],
                                              bool scatter, const RunSum& rs = RunSum{}) {
-  float pxa[D] = {};
+  // d/dx_p of sum_i v_i . (v~ + B (x_i - x_p)) w_ip: the weight-gradient term
+  // per node, and -B^T sum_i w_ip v_i once (that sum is wv).
+  float pxa[D] = {}, wv[D] = {};
   const AffineTab<D> rt(st, vt, Bm);  // r = v~ + B (x_i - x_p)
   for_nodes<D, S0>(st, [&](int o0, int o1, int o2) {
     float v[D];
@@ -1359,6 +1366,7 @@ __device__ __forceinline__ void g2p_adj_body(const StepConsts& k, const Sten<D>&
     for (int c = 0; c < D; ++c) {
       r[c] = rt.at(c, o0, o1, o2);
       vr += v[c] * r[c];
+      wv[c] += w * v[c];
     }
     if (scatter) {
       const int q = ad.idx(st, o0, o1, o2);
@@ -1376,13 +1384,13 @@ __device__ __forceinline__ void g2p_adj_body(const StepConsts& k, const Sten<D>&
       }
     }
 #pragma unroll
-    for (int e = 0; e < D; ++e) {
-      float Btv = 0.0f;
-#pragma unroll
-      for (int c = 0; c < D; ++c) Btv += Bm[c][e] * v[c];
-      pxa[e] += vr * dw[e] - w * Btv;
-    }
+    for (int e = 0; e < D; ++e) pxa[e] += vr * dw[e];
   });
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) pxa[e] -= Bm[c][e] * wv[c];
+  }
   quad_reduce<S0>(pxa);
 #pragma unroll
   for (int e = 0; e < D; ++e) px[e] += pxa[e];
