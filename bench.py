@@ -188,6 +188,30 @@ def wg_clock_summary(torch, sim, run, rows):
     return out
 
 
+def box_atomics(torch, L, n=64, launches=400):
+    """Mean time per launch of the atomic-layout microbenchmark
+    (mpm_diag_box_atomics): 128 workgroups adding overlapping 245-node boxes
+    of four components into an n^3 grid, back to back on one stream."""
+    g = torch.zeros(4 * n ** 3, device="cuda")
+    stream = torch.cuda.current_stream()
+    names = {0: "node per lane, instruction per component", 1: "lanes over (node, component)",
+             2: "plain stores, lanes over (node, component)", 3: "empty launch"}
+    out = {}
+    for _ in range(3):  # the smallest of three rounds over the layouts
+        for layout, name in names.items():
+            L.call("mpm_diag_box_atomics", layout, g.data_ptr(), n, 20, stream.cuda_stream)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            L.call("mpm_diag_box_atomics", layout, g.data_ptr(), n, launches, stream.cuda_stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = round(e0.elapsed_time(e1) * 1e3 / launches, 3)
+            out[name] = min(out.get(name, us), us)
+    return out
+
+
 COPY_MIB = 64  # calibration copy: reads and writes exactly this many MiB
 
 
@@ -681,6 +705,8 @@ def main():
                     help="smoke workload only (--steps trajectories), for rocprofv3 runs")
     ap.add_argument("--profile-batched", action="store_true",
                     help="batched 2D workload only (--steps trajectories), then one calibration copy")
+    ap.add_argument("--profile-atomics", action="store_true",
+                    help="atomic-layout microbenchmark of the scatter-tile flush pattern (one JSON line)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic record from two rocprofv3 --pmc runs of --profile")
     ap.add_argument("--pmc-command", default="", help="command recorded with --summarize-pmc")
@@ -700,6 +726,9 @@ def main():
     from paper_1910_00935_amd import runtime as rt
     from paper_1910_00935_amd import scenes
     torch.cuda.set_device(0)
+    if args.profile_atomics:
+        print(json.dumps({"profile": "box_atomics", "us_per_launch": box_atomics(torch, _lib)}), flush=True)
+        return
     if args.profile_smoke:
         # The smoke workload's forward, loss and reverse, --steps times, for rocprofv3 runs.
         sc = scenes.smoke()

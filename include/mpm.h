@@ -239,6 +239,20 @@ mpm_status mpm_wg_clock_bind(mpm_ctx* ctx, void* buf, size_t bytes);
 mpm_status mpm_wg_clock_info(const mpm_ctx* ctx, int32_t* launches, int32_t* stride, int32_t* kind, int32_t* wgs,
                              int32_t max_rows, int32_t* rate_khz);
 
+/* Atomic-layout microbenchmark (measurement support, not part of the method):
+ * enqueues `launches` back-to-back launches on `stream`, each of 128
+ * workgroups of 256 threads adding a 7 x 7 x 5 box of grid nodes of four
+ * floats into `grid` (caller-owned device memory of 4 * n^3 floats, n >= 34,
+ * node index z fastest, contents overwritten with meaningless sums), the
+ * boxes overlapping by three nodes along each axis like the scatter boxes of
+ * the 3D lattice workload. layout 0: one node per lane, one atomic instruction
+ * per component (the scatter-tile flush's earlier layout); 1: lanes over
+ * (node, component), component fastest (the flush's layout); 2: layout 1
+ * with plain stores; 3: no memory operation (launch cost only). The caller
+ * times the launches (events around the call). MPM_E_ARG on a null grid, n
+ * outside 34..1024, a negative count or an unknown layout. */
+mpm_status mpm_diag_box_atomics(int32_t layout, float* grid, int32_t n, int32_t launches, void* stream);
+
 /* One forward step, state `in` (step `step`) -> `out` (step + 1), in the
  * caller's particle order: clear_grid, compute_actuation (row `step` of
  * params->act), p2g, grid_op, g2p (Appendix D.1 stage order). `in` and `out`

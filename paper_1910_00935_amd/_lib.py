@@ -102,6 +102,7 @@ _SIGNATURES = {
     "mpm_tile_stats": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_int64)]),
     "mpm_wg_clock_bind": (c_int32, [c_void_p, c_void_p, c_size_t]),
+    "mpm_diag_box_atomics": (c_int32, [c_int32, c_void_p, c_int32, c_int32, c_void_p]),
     "mpm_wg_clock_info": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
                                     ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), c_int32,
                                     ctypes.POINTER(c_int32)]),

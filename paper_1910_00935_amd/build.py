@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmpm.so")
-SOURCES = [os.path.join(CSRC, "mpm.hip"), os.path.join(CSRC, "smoke.hip")]
+SOURCES = [os.path.join(CSRC, "mpm.hip"), os.path.join(CSRC, "smoke.hip"), os.path.join(CSRC, "diag.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")] + [
     os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE) if f.endswith(".h")]
 
