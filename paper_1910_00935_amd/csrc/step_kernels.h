@@ -702,6 +702,24 @@ struct Box {
   float bmax;
 };
 
+// Wavefront min / max of an int with DPP row shifts and row broadcasts (one
+// VALU instruction per step instead of a cross-lane LDS permute): after the
+// four shifts lane 15 of each row of 16 holds its row's result, the two
+// broadcasts carry it to lane 63, which is read back uniformly. Lanes whose
+// DPP source lies outside the row read the identity.
+template <bool MAX>
+__device__ __forceinline__ int wave_extreme(int v) {
+  constexpr int id = MAX ? INT_MIN : INT_MAX;
+  auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x111, 0xF, 0xF, false));  // row_shr:1
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x112, 0xF, 0xF, false));  // row_shr:2
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x114, 0xF, 0xF, false));  // row_shr:4
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x118, 0xF, 0xF, false));  // row_shr:8
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
 // Min/max of the stencil bases of the valid lanes and max of `bound` (a
 // non-negative contribution bound; NaN counts as +inf). All threads call.
 template <int D>
@@ -715,14 +733,11 @@ __device__ Box<D> block_reduce(bool valid, const int (&base)[D], float bound, Bl
   const float bb = (bound == bound) ? fmaxf(bound, 0.0f) : __int_as_float(0x7f800000);
   int b = __float_as_int(bb);  // non-negative floats order as ints
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      mn[a] = min(mn[a], __shfl_xor(mn[a], off, 64));
-      mx[a] = max(mx[a], __shfl_xor(mx[a], off, 64));
-    }
-    b = max(b, __shfl_xor(b, off, 64));
+  for (int a = 0; a < D; ++a) {
+    mn[a] = wave_extreme<false>(mn[a]);
+    mx[a] = wave_extreme<true>(mx[a]);
   }
+  b = wave_extreme<true>(b);
   int* s = r.sh + (r.phase & 1) * 32;
   const int w = int(threadIdx.x >> 6), nw = r.nw;
   if ((threadIdx.x & 63) == 0) {
