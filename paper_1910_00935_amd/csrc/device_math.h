@@ -436,11 +436,28 @@ __device__ __forceinline__ float liquid_adjoint(const PState<D>& p, const SceneP
 
 __device__ __forceinline__ bool interior1(int i, int n, int bound) { return i >= bound && i < n - bound; }
 
-// Warp (wave64) sum.
+// v of the DPP source lane (row shift or row broadcast `CTRL`, rows `ROWS`),
+// 0 where the source lies outside the row or the row is not written.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Wavefront (64-lane) sum, the same value in every lane: DPP row shifts
+// within rows of 16, then row broadcasts into lane 63, read back (one VALU
+// move per half and step instead of a cross-lane LDS permute). All lanes
+// must be active.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_move<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_move<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_move<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_move<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15
+  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
 
 }  // namespace mpm
