@@ -1670,7 +1670,7 @@ __device__ __forceinline__ void wave_add_keyed(bool live, int key, double val, d
   const int lane = threadIdx.x & 63;
   while (mask) {
     const int leader = __ffsll((long long)mask) - 1;
-    const int kk = __shfl(key, leader, 64);
+    const int kk = __builtin_amdgcn_readlane(key, leader);
     const bool mine = live && key == kk;
     const double s = wave_sum(mine ? val : 0.0);
     if (lane == leader) atomic_add_f64(base + kk, s);
