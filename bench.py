@@ -720,7 +720,7 @@ def main():
         summarize_pmc(*args.summarize_pmc, json.loads(args.knobs) if args.knobs else {}, args.pmc_command)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build's path runs on a single MI355X "
+        print(f"bench.py measures one GPU: the simulator runs on a single MI355X "
               f"(--gpus {args.gpus} is not supported)", file=sys.stderr)
         sys.exit(2)
     import torch
