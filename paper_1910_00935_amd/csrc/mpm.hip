@@ -102,6 +102,7 @@ struct mpm_ctx {
   int model = 0;     // constitutive model: 0 neo-Hookean, 1 fixed-corotated (MPM_MODEL_COROTATED)
   int n_blocks = 0;  // workgroups per particle pass for the current block and lanes
   int n_plain = 0;   // workgroups of the plain partition
+  int n_cus = 0;     // compute units of the device (0: not known)
   // Host copy of the caller-order workgroup table of single steps (R_BLOCKS:
   // the plain partition padded to n_blocks entries), empty when the launch
   // needs none (one scene, plain partition).
@@ -443,7 +444,11 @@ mpm_status launch_bwd(const mpm_ctx& c, const BwdArgs& args, hipStream_t st) {
   BwdArgs a = args;
   a.k.threads = c.block;
   a.k.clear_per_role = c.part ? c.n_plain : c.n_blocks;
-  a.k.groups = (args.split_c ? 2 : 1) * a.k.clear_per_role;
+  // With a separate recompute role the clears go to both roles, or to the
+  // recompute role alone when every workgroup of the launch has a compute
+  // unit of its own (the kernel reads which from groups).
+  const bool clears_c_only = args.split_c && c.n_cus > 0 && nb <= c.n_cus;
+  a.k.groups = (args.split_c && !clears_c_only ? 2 : 1) * a.k.clear_per_role;
   if (c.rec_bwd) {
     c.rec_bwd->push_back(a);
     return MPM_OK;
@@ -903,6 +908,14 @@ mpm_status mpm_init(const mpm_desc* desc, mpm_ctx** out) {
   c->gravity = d.gravity;
   c->act_strength = d.act_strength;
   c->offsets.assign(d.scene_offsets, d.scene_offsets + d.n_scenes + 1);
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      c->n_cus = cus;
+    else
+      (void)hipGetLastError();  // unknown: the reverse launches spread their clears over both roles
+  }
   int bits = 0;
   while ((1 << bits) < d.n_grid) ++bits;
   c->bits = bits;

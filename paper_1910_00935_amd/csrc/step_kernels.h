@@ -72,7 +72,7 @@ struct StepConsts {
   int n_blocks;         // workgroups per particle pass
   int threads;          // threads per workgroup of this launch (blockDim.x, kept in a scalar register)
   int groups;           // workgroups that share the launch's clears (their clear ranks 0..groups-1)
-  int clear_per_role;   // of each role's n_blocks workgroups, the first clear_per_role take part in clears
+  int clear_per_role;   // of each clearing role's n_blocks workgroups, the first clear_per_role take part
   const float* E;
   const float* nu;
   const float* vol;
@@ -341,12 +341,12 @@ __device__ __forceinline__ void clear_entry(const ClearSpec& s0, const ClearSpec
 }
 
 // Clear rank of a workgroup: its index among the workgroups that take part in
-// the launch's clears, or -1. Of each role's n_blocks workgroups (one role, or
-// two with a separate recompute role), the first clear_per_role do; the
-// aligned partition's trailing empty workgroups therefore never do.
-__device__ __forceinline__ int clear_rank(const StepConsts& k, int wg, bool second_role) {
-  if (wg >= k.clear_per_role) return -1;
-  return second_role ? k.clear_per_role + wg : wg;
+// the launch's clears, or -1. Of each clearing role's n_blocks workgroups the
+// first clear_per_role do (the aligned partition's trailing empty workgroups
+// therefore never do); `offset` places a second role's ranks after the
+// first's.
+__device__ __forceinline__ int clear_rank(const StepConsts& k, int wg, bool takes_clears, int offset) {
+  return (takes_clears && wg < k.clear_per_role) ? offset + wg : -1;
 }
 
 template <bool P>
@@ -1604,7 +1604,7 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int wgi, FwdShared<D
   const int sc = lm.scene;
   const bool one_scene = true;
   unsigned err = 0;
-  const int rank = clear_rank(k, wgi, false);
+  const int rank = clear_rank(k, wgi, true, 0);
   if (k.blocks && lm.count == 0 && rank < 0) {  // an unused entry of the aligned partition
     if (a.do_p2g) record_box<D>(a.box_out, wgi, empty_tile<D>(), -1);
     return;
@@ -1709,7 +1709,13 @@ __device__ __forceinline__ void bwd_block(const BwdArgs& a, int wgi, BwdShared<D
   const int sc = lm.scene;
   const bool one_scene = true;
   unsigned err = 0;
-  const int rank = clear_rank(k, wg, role_c);
+  // With the recompute role, the clears are spread over both roles (groups =
+  // 2 clear_per_role) or, when every workgroup of the launch has a compute
+  // unit of its own, all given to the recompute role (groups =
+  // clear_per_role): its workgroups end well before the adjoint ones, whose
+  // chain then sets the launch's duration.
+  const bool c_clears_only = a.split_c && k.groups == k.clear_per_role;
+  const int rank = clear_rank(k, wg, role_c || !c_clears_only, (role_c && !c_clears_only) ? k.clear_per_role : 0);
   if (k.blocks && lm.count == 0 && rank < 0) {  // an unused entry of the aligned partition
     if (role_c) {
       record_box<D>(a.boxC, wg, empty_tile<D>(), -1);
