@@ -417,22 +417,27 @@ mpm_status launch_fwd(const mpm_ctx& c, const FwdArgs& args, hipStream_t st, boo
   a.k.clear_per_role = c.part ? c.n_plain : c.n_blocks;
   a.k.groups = a.k.clear_per_role;
   if (c.rec_fwd) {
-    c.rec_fwd->push_back(a);
+    c.rec_fwd->push_back(a);  // the persistent form's stepping workgroups clear
     return MPM_OK;
   }
-  clock_row(c, a.k, MPM_KERNEL_FWD, c.n_blocks);
+  // When the stepping workgroups leave compute units idle, as many more
+  // workgroups take the clears instead (every launch, so each launch of a
+  // sequence has the same shape).
+  a.clear_wgs = (c.n_cus > 0 && 2 * c.n_blocks <= c.n_cus) ? a.k.clear_per_role : 0;
+  const int wgs = c.n_blocks + a.clear_wgs;
+  clock_row(c, a.k, MPM_KERNEL_FWD, wgs);
   if (timed) span_step(c, 0, st);
   const bool pre = LPP == 1 && c.presum;
   if (c.model == 1) {
     if (pre)
-      hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 1, LPP == 1>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
+      hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 1, LPP == 1>), dim3(wgs), dim3(c.block), 0, st, a);
     else
-      hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 1>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
+      hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 1>), dim3(wgs), dim3(c.block), 0, st, a);
   } else {
     if (pre)
-      hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 0, LPP == 1>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
+      hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 0, LPP == 1>), dim3(wgs), dim3(c.block), 0, st, a);
     else
-      hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 0>), dim3(c.n_blocks), dim3(c.block), 0, st, a);
+      hipLaunchKernelGGL((mpm::k_fwd<D, LPP, 0>), dim3(wgs), dim3(c.block), 0, st, a);
   }
   LAUNCH_TRY();
   return MPM_OK;

@@ -101,6 +101,7 @@ struct FwdArgs {
   long clear_n;            // float4 count (dense clear)
   const int4* clear_box;   // or: the boxes its last scatter recorded (clear_nbox workgroups)
   int clear_nbox;
+  int clear_wgs;           // workgroups after the k.n_blocks stepping ones that only clear (0: the stepping ones clear)
   int4* box_out;           // box table of grid_out (record_box), or null
   const int4* box_in;      // box table the scatter into grid_in recorded (this launch's workgroups), or null
 };
@@ -1596,6 +1597,14 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int wgi, FwdShared<D
   long long* tile64 = sh.tile64;
   float* vtile = sh.vtile;
   const StepConsts& k = a.k;
+  const ClearSpec c0{a.clear, a.clear_box, a.clear_nbox, a.clear_n}, c1{nullptr, nullptr, 0, 0};
+  if (a.clear_wgs && wgi >= k.n_blocks) {
+    // A workgroup that only clears: the launch's clears then stay off the
+    // stepping workgroups' chain, on compute units they leave idle.
+    const int rank = clear_rank(k, wgi - k.n_blocks, true, 0);
+    clear_jobs_run<D, P>(clear_jobs_fetch<P>(c0, c1, rank, k.groups), c0, c1, k, rank);
+    return;
+  }
   BlockRed rd{sh.red, 0, (k.threads + 63) >> 6};
   const LaneMap<LPP> lm(k, wgi);
   const int i = lm.i, sub = lm.sub;
@@ -1604,7 +1613,7 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int wgi, FwdShared<D
   const int sc = lm.scene;
   const bool one_scene = true;
   unsigned err = 0;
-  const int rank = clear_rank(k, wgi, true, 0);
+  const int rank = clear_rank(k, wgi, !a.clear_wgs, 0);
   if (k.blocks && lm.count == 0 && rank < 0) {  // an unused entry of the aligned partition
     if (a.do_p2g) record_box<D>(a.box_out, wgi, empty_tile<D>(), -1);
     return;
@@ -1615,7 +1624,6 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a, int wgi, FwdShared<D
   // reduction and its latency overlaps the state's.
   PState<D> p;
   if (live) load_state<D>(a.in, i, p);
-  const ClearSpec c0{a.clear, a.clear_box, a.clear_nbox, a.clear_n}, c1{nullptr, nullptr, 0, 0};
   const ClearJobs cj = clear_jobs_fetch<P>(c0, c1, rank, k.groups);
   if (a.do_p2g && k.lds) zero_tile64<D, D + 1>(tile64, k.threads);
   Tile<D> T = empty_tile<D>();
