@@ -232,7 +232,10 @@ mpm_status mpm_tile_stats(mpm_ctx* ctx, void* stream, int64_t* lds_scatters, int
 mpm_status mpm_wg_clock_bind(mpm_ctx* ctx, void* buf, size_t bytes);
 
 /* Rows taken since the last bind: *launches rows; for row r < max_rows,
- * kind[r] (MPM_KERNEL_FWD / MPM_KERNEL_BWD) and wgs[r] (its workgroups); the
+ * kind[r] (MPM_KERNEL_FWD / MPM_KERNEL_BWD) and wgs[r] (its workgroups: a
+ * forward launch's stepping workgroups, followed, when they fill at most half
+ * of the device's compute units, by as many that only clear grid memory; a
+ * reverse launch's adjoint workgroups, then its recompute workgroups); the
  * row stride in workgroups (with no buffer bound: the stride a bind would
  * take now) and the clock's rate in kHz (the device's wall clock rate). Any
  * output pointer may be null. */
