@@ -919,7 +919,7 @@ mpm_status mpm_init(const mpm_desc* desc, mpm_ctx** out) {
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
       c->n_cus = cus;
     else
-      (void)hipGetLastError();  // unknown: the reverse launches spread their clears over both roles
+      (void)hipGetLastError();  // unknown: the step launches keep their clears on their own workgroups
   }
   int bits = 0;
   while ((1 << bits) < d.n_grid) ++bits;
